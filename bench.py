@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Benchmark of the explicit 3-D heat-diffusion step on one MI355X.
+
+A bench step is one call of the library's time loop: nt = 100 steps of the
+512^3 FP64 bump workload (T0 = Gaussian bump + 0.01*U[0,1], Ci = 0.5*(1+0.5u),
+dt by the 6.1 rule; the grid and precision of the paper's Fig. 1 listing).
+The headline value is the effective memory throughput
+    T_eff = 3 * sizeof(dtype) * nx*ny*nz / t_step      (GB/s, 1e9 bytes)
+(read T, read Ci, write T2 per step), with t_step the time of one diffusion
+step.  Printed as one JSON line, with the roofline of the step kernel, the
+measured copy bandwidth, the reduced-precision forms, the adjoint/forward
+time ratio and the oracle timed on the host (CPU baseline).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_step_zmarch_bump512_f64.json")
+METRIC = "T_eff GB/s (% HBM peak) per 3-D diffusion step; adjoint/forward time ratio"
+
+
+def kernel_source_hash() -> str:
+    csrc = os.path.join(ROOT, "paper_2211_15634_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "include", "diff3d.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def median_ci(xs):
+    """Median and an approximate 95% confidence interval of the median
+    (order statistics of the binomial(n, 1/2) around n/2)."""
+    xs = sorted(xs)
+    n = len(xs)
+    med = statistics.median(xs)
+    if n < 6:
+        return med, xs[0], xs[-1]
+    k = int(math.floor(n / 2 - 1.96 * math.sqrt(n) / 2))
+    j = int(math.ceil(n / 2 + 1.96 * math.sqrt(n) / 2))
+    return med, xs[max(k, 0)], xs[min(j, n - 1)]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--nt", type=int, default=100)
+    ap.add_argument("--quick", action="store_true", help="headline only: no precision, adjoint or CPU legs")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the 3-D diffusion step here runs on a single MI355X "
+              "(multi-GPU halo exchange is not part of this build); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2211_15634_amd as d3
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, nt = args.n, args.nt
+    N = n * n * n
+    log("bench: generating bump%d inputs" % n)
+    T0h, Cih = workloads.bump(n, n, n)
+    T0 = torch.from_numpy(T0h).to(dev)
+    Ci = torch.from_numpy(Cih).to(dev)
+    s = d3.problem_scalars(Ci)
+    T = T0.clone()
+    T2 = torch.empty_like(T)
+    sc = (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+    stream = torch.cuda.current_stream(dev)
+
+    # ---------------------------------------------------------- headline
+    log("bench: warmup %d x run(nt=%d)" % (args.warmup, nt))
+    for _ in range(args.warmup):
+        d3.run(T, T2, Ci, *sc, nt)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for k in range(args.steps):
+        d3.run(T, T2, Ci, *sc, nt)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_run_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    total_ms = evs[0].elapsed_time(evs[-1])
+    ms_per_step = total_ms / args.steps
+    t_step = ms_per_step / 1e3 / nt
+    bytes_step = 3 * 8 * N
+    teff = bytes_step / t_step / 1e9
+    med, lo, hi = median_ci(per_run_ms)
+    if not torch.isfinite(T).all():
+        raise RuntimeError("non-finite values after the timed runs")
+    log("bench: %.3f ms per run of %d steps, T_eff %.1f GB/s (wall %.3f s)" % (ms_per_step, nt, teff, wall))
+
+    # ---------------------------------------------------------- kernel duration
+    # one diff3d_step launch between two events, on the stream it runs on
+    M = 40
+    kev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * M)]
+    a, b = T, T2
+    for i in range(M):
+        kev[2 * i].record(stream)
+        d3.step(b, a, Ci, *sc)
+        kev[2 * i + 1].record(stream)
+        a, b = b, a
+    torch.cuda.synchronize()
+    kms = [kev[2 * i].elapsed_time(kev[2 * i + 1]) for i in range(M)]
+    k_avg_ms = sum(kms) / M
+    achieved = bytes_step / (k_avg_ms / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == kernel_source_hash() and tr.get("workload") == "bump%d_f64" % n:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "step_zmarch", "kernel_avg_us": round(k_avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": bytes_step}
+    log("bench: step kernel %.1f us, %.1f GB/s" % (k_avg_ms * 1e3, achieved))
+
+    # ---------------------------------------------------------- copy bandwidth
+    del T2
+    torch.cuda.empty_cache()
+    cb = 4 << 30
+    src = torch.empty(cb, dtype=torch.uint8, device=dev)
+    dst = torch.empty(cb, dtype=torch.uint8, device=dev)
+    src.fill_(1)
+    for _ in range(2):
+        d3.copy_(dst, src)
+    cev = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+    cev[0].record(stream)
+    for i in range(10):
+        d3.copy_(dst, src)
+        cev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    cms = sorted(cev[i].elapsed_time(cev[i + 1]) for i in range(10))
+    copy_gbps = 2 * cb / (statistics.median(cms) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    log("bench: copy %.1f GB/s" % copy_gbps)
+
+    extra = {}
+    if not args.quick:
+        # ------------------------------------------------------ precision forms
+        T2 = torch.empty_like(T)
+        for name, tdt, rounding in (("f32", torch.float32, "sr"), ("bf16_sr", torch.bfloat16, "sr"),
+                                    ("bf16_rne", torch.bfloat16, "rne")):
+            Tl = T0.to(tdt)
+            T2l = torch.empty_like(Tl)
+            Cl = Ci.to(tdt)
+            d3.run(Tl, T2l, Cl, *sc, nt, rounding=rounding)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                d3.run(Tl, T2l, Cl, *sc, nt, rounding=rounding)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts = e0.elapsed_time(e1) / 3 / 1e3 / nt
+            esz = Tl.element_size()
+            extra["teff_%s_GBps" % name] = round(3 * esz * N / ts / 1e9, 1)
+            extra["t_step_%s_us" % name] = round(ts * 1e6, 2)
+            extra["speedup_%s_vs_f64" % name] = round(t_step / ts, 3)
+            del Tl, T2l, Cl
+        del T2
+        torch.cuda.empty_cache()
+        log("bench: precision forms", extra)
+
+        # ------------------------------------------------------ adjoint ratio
+        for tdt, tag in ((torch.float64, "f64"), (torch.float32, "f32")):
+            m, ntg, C = 256, 200, 14
+            x, cc = workloads.uniform_const(m, m, m)
+            tt = workloads.target(m, m, m)
+            X0 = torch.from_numpy(x).to(dev, tdt)
+            Cg = torch.from_numpy(cc).to(dev, tdt)
+            Tt = torch.from_numpy(tt).to(dev, tdt)
+            sg = d3.problem_scalars(Cg)
+            scg = (sg["lam"], sg["dt"], sg["rdx"], sg["rdy"], sg["rdz"])
+            ws = torch.empty(d3.adjoint_workspace_bytes(X0.shape, ntg, C, tdt), dtype=torch.uint8, device=dev)
+            Tg, T2g = X0.clone(), torch.empty_like(X0)
+            seed, gT0, gCi = torch.empty_like(X0), torch.empty_like(X0), torch.empty_like(X0)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            for rep in range(2):   # the first repetition warms up
+                Tg.copy_(X0)
+                ev[0].record(stream)
+                d3.run(Tg, T2g, Cg, *scg, ntg, ckpt=ws, ckpt_every=C)
+                ev[1].record(stream)
+                d3.loss(Tg, Tt, seed)
+                ev[2].record(stream)
+                d3.adjoint_run(X0, Cg, seed, gT0, gCi, ws, True, *scg, ntg, C)
+                ev[3].record(stream)
+                torch.cuda.synchronize()
+            tf = ev[0].elapsed_time(ev[1])
+            tb = ev[2].elapsed_time(ev[3])
+            extra["adjoint_%s_256_fwd_ms" % tag] = round(tf, 3)
+            extra["adjoint_%s_256_bwd_ms" % tag] = round(tb, 3)
+            extra["adjoint_%s_256_ratio" % tag] = round(tb / tf, 3)
+            extra["adjoint_%s_256_gradnorm" % tag] = float(d3.norm2(gT0)) ** 0.5
+            del X0, Cg, Tt, ws, Tg, T2g, seed, gT0, gCi
+            torch.cuda.empty_cache()
+        log("bench: adjoint", {k: v for k, v in extra.items() if k.startswith("adjoint")})
+
+    # ---------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu and not args.quick:
+        import oracle
+        threads = oracle.max_threads()
+        # a bounded sample: the oracle on the same 512^3 inputs, k steps, sized
+        # from a one-step probe to about --cpu-seconds of work
+        t1 = time.perf_counter()
+        oracle.forward(T0h, Cih, *sc, 1)
+        probe = time.perf_counter() - t1
+        k = max(1, min(nt, int(args.cpu_seconds / max(probe, 1e-3))))
+        t1 = time.perf_counter()
+        oracle.forward(T0h, Cih, *sc, k)
+        tc = time.perf_counter() - t1
+        cpu_teff = bytes_step * k / tc / 1e9
+        cpu = {"value": round(cpu_teff, 2), "unit": "GB/s", "cores": threads, "kind": "oracle",
+               "sample": "oracle FP64 forward on the same bump 512^3 inputs, %d step(s) (plus its two "
+                         "initial field copies), %.1f s" % (k, tc),
+               "t_step_s": round(tc / k, 4)}
+        log("bench: cpu oracle", cpu)
+
+    out = {
+        "metric": METRIC,
+        "value": round(teff, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "bump%d FP64: 3-D heat diffusion %d^3, nt=%d per step, Gaussian bump + 0.01 U[0,1] "
+                               "noise, Ci=0.5(1+0.5u), lam=1, dt=min(dx^2)/lam/max(Ci)/6.1" % (n, n, nt),
+                   "nx": n, "ny": n, "nz": n, "nt": nt, "kernel": "zmarch", "parallelism": "single GPU"},
+        "t_step_us": round(t_step * 1e6, 3),
+        "teff_frac_hbm_peak": round(teff / HBM_PEAK_GBPS, 4),
+        "copy_GBps": round(copy_gbps, 1),
+        "teff_frac_copy": round(teff / copy_gbps, 4),
+        "run_ms_median": round(med, 4),
+        "run_ms_ci95": [round(lo, 4), round(hi, 4)],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

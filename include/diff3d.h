@@ -1,0 +1,171 @@
+/*
+ * diff3d: explicit 3-D heat diffusion on one MI355X (gfx950), C ABI.
+ *
+ * The operation is the time step of Omlin & Raess, "High-performance xPU
+ * Stencil Computations in Julia" (JuliaCon 2019), Fig. 1 (kernel `step!` and
+ * driver `diffusion3D`):
+ *
+ *   on interior points (1 <= ix <= nx-2, same for y and z)
+ *     T2 = T + dt*((lam*Ci)*((d2x(T)*cx + d2y(T)*cy) + d2z(T)*cz))
+ *   with d2x(A) = (A[x+1] - A[x]) - (A[x] - A[x-1]) (likewise y, z) and
+ *   cx = rdx*rdx, rdx = 1/dx (likewise y, z); boundary points are never
+ *   written (fixed values); the two buffers then swap roles.
+ *
+ * Added to the paper's method: reduced-precision storage (FP32, BF16 with
+ * FP32 arithmetic) and a checkpointed reverse sweep (adjoint) giving the
+ * gradient of a loss of T_nt with respect to T0 and Ci.
+ *
+ * Conventions for every entry point:
+ *  - Fields are dense nx*ny*nz arrays in device memory with linear index
+ *    ix + nx*(iy + ny*iz): x is contiguous (the paper's column-major Julia
+ *    arrays).  A torch tensor of shape (nz, ny, nx), contiguous, has this
+ *    layout.  Element type is given by `dtype` (diff3d_dtype).
+ *  - All buffers are owned by the caller.  The library never allocates or
+ *    frees device memory and keeps no pointer after a call returns.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work on it and return without synchronising, except where stated.
+ *  - Scalars are passed as double.  FP32/BF16 forms round each of lam, dt
+ *    and (1/h)^2 once to float.
+ *  - Return value is a diff3d_status.  Arguments are validated on the host
+ *    before anything is enqueued; on error nothing is enqueued.  Errors from
+ *    the HIP runtime (launch failures) are reported as DIFF3D_EHIP.
+ *  - Sizes: each of nx, ny, nz must be >= 3 (a grid with an interior) and
+ *    nx*ny*nz < 2^40.
+ */
+#ifndef DIFF3D_H
+#define DIFF3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DIFF3D_F64 = 0,       /* FP64 storage, FP64 arithmetic (the paper's Float64) */
+    DIFF3D_F32 = 1,       /* FP32 storage, FP32 arithmetic */
+    DIFF3D_BF16 = 2,      /* BF16 storage, FP32 arithmetic, stores rounded stochastically */
+    DIFF3D_BF16_RNE = 3   /* BF16 storage, FP32 arithmetic, stores rounded to nearest even */
+} diff3d_dtype;
+
+typedef enum {
+    DIFF3D_OK = 0,
+    DIFF3D_EINVAL = -1,      /* bad pointer, size, count or aliasing */
+    DIFF3D_EDTYPE = -2,      /* unknown dtype, or dtype not supported by this entry point */
+    DIFF3D_EWORKSPACE = -3,  /* workspace missing or smaller than required */
+    DIFF3D_EHIP = -4         /* the HIP runtime reported an error */
+} diff3d_status;
+
+typedef enum {
+    DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant for the shape */
+    DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */
+    DIFF3D_KERNEL_ZMARCH = 2   /* x-y tiles marching along z, planes in registers and LDS */
+} diff3d_kernel;
+
+/* Number of doubles in the device buffer `acc` of the reductions below. */
+#define DIFF3D_REDUCE_DOUBLES 1025
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* diff3d_strerror(int status);
+
+/* Element size in bytes of a dtype, or 0 if unknown. */
+size_t diff3d_dtype_size(int dtype);
+
+/* Driver scalars of Fig. 1 (host arithmetic only, no GPU work):
+ *   dx = lx/(nx-1), dy, dz likewise; rdx = 1.0/dx etc.;
+ *   dt = min(dx*dx, dy*dy, dz*dz)/lam/cimax/6.1, evaluated left to right,
+ * where cimax is the maximum of Ci over the whole array (diff3d_max).
+ * out receives {dx, dy, dz, rdx, rdy, rdz, dt}.  EINVAL if out is NULL,
+ * a size is < 3, or lam or cimax is not positive. */
+int diff3d_scalars(int nx, int ny, int nz, double lx, double ly, double lz, double lam,
+                   double cimax, double* out);
+
+/* Maximum of n elements of x (device, `dtype`), written as a double to
+ * acc[0].  acc is a device buffer of DIFF3D_REDUCE_DOUBLES doubles used as
+ * scratch; the result is deterministic. */
+int diff3d_max(const void* x, size_t n, int dtype, double* acc, void* stream);
+
+/* One time step (Fig. 1, `step!`).  Writes the interior of T2 from T and Ci;
+ * T2's boundary is not touched (the caller keeps it equal to T's, as
+ * T2 = copy(T) does in the paper).  T2 must not alias T or Ci.
+ * For DIFF3D_BF16 the stochastic rounding draws from the counter
+ * (seed, step_index, point), see diff3d_set_sr_seed. */
+int diff3d_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
+                double dt, double rdx, double rdy, double rdz, int dtype, void* stream);
+
+/* nt time steps with the buffer swap of Fig. 1.  First copies T's boundary
+ * into T2, then alternates steps T -> T2 -> T ...  The result T_nt is always
+ * left in T (one extra copy when nt is odd); T2 is scratch.
+ * Checkpoints: if ckpt is not NULL, the states T_{j*C} for j = 1 .. nck-1,
+ * C = ckpt_every, nck = ceil(nt/C), are copied into consecutive fields of
+ * ckpt (field j-1 holds T_{j*C}); this is the first part of the workspace
+ * of diff3d_adjoint_run, which can then be called with ckpt_ready = 1.
+ * ckpt_every must be >= 1 when ckpt is given.  nt = 0 leaves T unchanged. */
+int diff3d_run(void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt,
+               double rdx, double rdy, double rdz, int nt, int dtype, void* stream, void* ckpt,
+               int ckpt_every);
+
+/* Bytes of workspace for diff3d_adjoint_run: (nck - 1) checkpoint fields,
+ * (C - 1) fields for the states recomputed inside a segment and one field
+ * for the adjoint ping-pong, each nx*ny*nz*sizeof(dtype), rounded up to
+ * 256-byte field boundaries.  Returns 0 for invalid arguments. */
+size_t diff3d_adjoint_workspace_bytes(int nx, int ny, int nz, int nt, int ckpt_every, int dtype);
+
+/* Reverse sweep of nt steps (the transpose of the step, derived by hand):
+ * given gTnt = dLoss/dT_nt, writes gT0 = dLoss/dT0 and overwrites gCi with
+ * dLoss/dCi (0 on the boundary).  Per step k = nt-1 .. 0, with
+ * lambda_nt = gTnt and c = dt*lam*Ci:
+ *   gCi += dt*lam*lambda_{k+1}*Lap(T_k)       on interior points
+ *   mu   = dt*lam*Ci*lambda_{k+1} on interior points, 0 elsewhere
+ *   lambda_k = lambda_{k+1} + Lap(mu)          at every point (mu = 0 outside)
+ * Lap is the weighted 7-point expression of the step.  States T_k are
+ * recomputed segment by segment from checkpoints every ckpt_every steps
+ * (computed here from T0 unless ckpt_ready = 1, in which case the workspace
+ * already holds them from diff3d_run with the same T0, Ci, scalars, nt,
+ * ckpt_every and dtype).  Only DIFF3D_F64 and DIFF3D_F32 are supported
+ * (EDTYPE otherwise).  gT0, gCi and the workspace must not overlap each
+ * other or the inputs. */
+int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* gT0, void* gCi,
+                       void* workspace, size_t ws_bytes, int ckpt_ready, int nx, int ny, int nz,
+                       double lam, double dt, double rdx, double rdy, double rdz, int nt,
+                       int ckpt_every, int dtype, void* stream);
+
+/* Loss of the gradient examples: L = 0.5*sum((T - Tt)^2) over all n points,
+ * accumulated in FP64 into acc[0] (acc: DIFF3D_REDUCE_DOUBLES doubles of
+ * device scratch; deterministic order), and the seed of the reverse sweep
+ * r = T - Tt written to `seed` (may be NULL) in the storage dtype. */
+int diff3d_loss(const void* T, const void* Tt, void* seed, size_t n, int dtype, double* acc,
+                void* stream);
+
+/* Squared 2-norm of n elements of x, accumulated in FP64 into acc[0]
+ * (deterministic order). */
+int diff3d_norm2(const void* x, size_t n, int dtype, double* acc, void* stream);
+
+/* Plain device copy of `bytes` bytes (16-byte vector loads and stores; the
+ * measured copy bandwidth is the reachable-peak reference).  dst and src
+ * must not overlap and must be 16-byte aligned. */
+int diff3d_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Process-wide settings (not thread safe; they apply to later calls). */
+/* Select the forward step variant (diff3d_kernel); EINVAL if unknown. */
+int diff3d_set_kernel(int kernel);
+int diff3d_get_kernel(void);
+/* Seed of the stochastic rounding of DIFF3D_BF16 and the step index the
+ * next diff3d_step uses; diff3d_run uses indices step0 .. step0+nt-1 and
+ * advances the index by nt, diff3d_step by 1. */
+void diff3d_set_sr_seed(uint64_t seed, uint64_t step0);
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the counter-based
+ * generator behind the stochastic rounding: out = bijection of ctr under
+ * key.  Host function (same code as on the device), for tests. */
+void diff3d_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Library version string. */
+const char* diff3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIFF3D_H */

@@ -1,0 +1,278 @@
+"""Python binding of libdiff3d, the MI355X (gfx950) 3-D heat-diffusion library.
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libdiff3d.so`` (built by ``paper_2211_15634_amd.build``).  PyTorch supplies
+device memory and the current stream.  If the library is missing this module
+raises ImportError: there is no fallback path.
+
+Method: the explicit time step of Omlin & Raess, "High-performance xPU
+Stencil Computations in Julia", Fig. 1 (``step!`` and the ``diffusion3D``
+driver), plus reduced-precision storage and a checkpointed adjoint.
+
+Fields are torch tensors of shape (nz, ny, nx), contiguous, on the GPU, of
+dtype float64, float32 or bfloat16 (x is the contiguous axis, as in the
+paper's column-major Julia arrays).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdiff3d.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdiff3d.so is not built; run `python -m paper_2211_15634_amd.build` "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+F64, F32, BF16, BF16_RNE = 0, 1, 2, 3
+OK, EINVAL, EDTYPE, EWORKSPACE, EHIP = 0, -1, -2, -3, -4
+KERNEL_AUTO, KERNEL_NAIVE, KERNEL_ZMARCH = 0, 1, 2
+REDUCE_DOUBLES = 1025
+
+_vp, _i, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+_dp = ctypes.POINTER(ctypes.c_double)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+_SIGS = {
+    "diff3d_strerror": ([_i], ctypes.c_char_p),
+    "diff3d_dtype_size": ([_i], _sz),
+    "diff3d_version": ([], ctypes.c_char_p),
+    "diff3d_scalars": ([_i, _i, _i, _d, _d, _d, _d, _d, _dp], _i),
+    "diff3d_max": ([_vp, _sz, _i, _vp, _vp], _i),
+    "diff3d_step": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _vp], _i),
+    "diff3d_run": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _vp, _vp, _i], _i),
+    "diff3d_adjoint_workspace_bytes": ([_i, _i, _i, _i, _i, _i], _sz),
+    "diff3d_adjoint_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _i, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _i,
+                            _vp], _i),
+    "diff3d_loss": ([_vp, _vp, _vp, _sz, _i, _vp, _vp], _i),
+    "diff3d_norm2": ([_vp, _sz, _i, _vp, _vp], _i),
+    "diff3d_copy": ([_vp, _vp, _sz, _vp], _i),
+    "diff3d_set_kernel": ([_i], _i),
+    "diff3d_get_kernel": ([], _i),
+    "diff3d_set_sr_seed": ([ctypes.c_uint64, ctypes.c_uint64], None),
+    "diff3d_philox4x32_10": ([_u32p, _u32p, _u32p], None),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTS = tuple(_SIGS)
+
+
+class Diff3dError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__("%s: %s (%d)" % (where, _lib.diff3d_strerror(status).decode(), status))
+        self.status = status
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise Diff3dError(rc, where)
+
+
+def _code(t: torch.Tensor, rounding: str = "sr") -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16 if rounding == "sr" else BF16_RNE
+    raise TypeError("unsupported dtype %s" % t.dtype)
+
+
+def _field(t: torch.Tensor, name: str, like: torch.Tensor | None = None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA/HIP tensor" % name)
+    if t.dim() != 3 or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous (nz, ny, nx) tensor" % name)
+    if like is not None and (t.shape != like.shape or t.dtype != like.dtype or t.device != like.device):
+        raise ValueError("%s must match shape/dtype/device of the other fields" % name)
+    return t
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def version() -> str:
+    return _lib.diff3d_version().decode()
+
+
+def strerror(status: int) -> str:
+    return _lib.diff3d_strerror(status).decode()
+
+
+def set_kernel(kind: int) -> None:
+    _check(_lib.diff3d_set_kernel(kind), "set_kernel")
+
+
+def get_kernel() -> int:
+    return _lib.diff3d_get_kernel()
+
+
+def set_sr_seed(seed: int, step0: int = 0) -> None:
+    _lib.diff3d_set_sr_seed(seed & (2 ** 64 - 1), step0 & (2 ** 64 - 1))
+
+
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    _lib.diff3d_philox4x32_10(c, k, o)
+    return tuple(o)
+
+
+def scalars(nx: int, ny: int, nz: int, cimax: float, lam: float = 1.0, lx: float = 1.0, ly: float = 1.0,
+            lz: float = 1.0) -> dict:
+    """Driver scalars of Fig. 1 (host arithmetic in the library)."""
+    out = (ctypes.c_double * 7)()
+    _check(_lib.diff3d_scalars(nx, ny, nz, lx, ly, lz, lam, cimax, out), "scalars")
+    keys = ("dx", "dy", "dz", "rdx", "rdy", "rdz", "dt")
+    res = {k: float(v) for k, v in zip(keys, out)}
+    res["lam"] = float(lam)
+    return res
+
+
+def _acc(device) -> torch.Tensor:
+    return torch.empty(REDUCE_DOUBLES, dtype=torch.float64, device=device)
+
+
+def field_max(x: torch.Tensor) -> torch.Tensor:
+    """max(x) as a 0-d float64 device tensor (deterministic reduction)."""
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous GPU tensor")
+    acc = _acc(x.device)
+    _check(_lib.diff3d_max(_p(x), x.numel(), _code(x), _p(acc), _stream(x)), "max")
+    return acc[0]
+
+
+def problem_scalars(Ci: torch.Tensor, lam: float = 1.0, lx: float = 1.0, ly: float = 1.0, lz: float = 1.0) -> dict:
+    """dx, dy, dz, their inverses and dt for the grid of Ci, with max(Ci)
+    reduced on the GPU (one device-to-host read)."""
+    nz, ny, nx = Ci.shape
+    cimax = float(field_max(Ci).item())
+    return scalars(nx, ny, nz, cimax, lam=lam, lx=lx, ly=ly, lz=lz)
+
+
+def step(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
+         rdz: float, rounding: str = "sr") -> None:
+    """One step: interior of T2 from T and Ci (T2's boundary untouched)."""
+    _field(T, "T")
+    _field(T2, "T2", T)
+    _field(Ci, "Ci", T)
+    nz, ny, nx = T.shape
+    _check(_lib.diff3d_step(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _code(T, rounding),
+                            _stream(T)), "step")
+
+
+def run(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
+        rdz: float, nt: int, rounding: str = "sr", ckpt: torch.Tensor | None = None, ckpt_every: int = 0) -> None:
+    """nt steps with the swap; the result is left in T (T2 is scratch).
+    ``ckpt`` (a uint8 device buffer, e.g. an adjoint workspace) receives
+    T_{j*ckpt_every} for j >= 1."""
+    _field(T, "T")
+    _field(T2, "T2", T)
+    _field(Ci, "Ci", T)
+    nz, ny, nx = T.shape
+    if ckpt is not None and (not ckpt.is_cuda or not ckpt.is_contiguous()):
+        raise ValueError("ckpt must be a contiguous GPU buffer")
+    _check(_lib.diff3d_run(_p(T), _p(T2), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nt), _code(T, rounding),
+                           _stream(T), _p(ckpt), int(ckpt_every)), "run")
+
+
+def adjoint_workspace_bytes(shape, nt: int, ckpt_every: int, dtype: torch.dtype) -> int:
+    nz, ny, nx = shape
+    code = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[dtype]
+    return int(_lib.diff3d_adjoint_workspace_bytes(nx, ny, nz, int(nt), int(ckpt_every), code))
+
+
+def adjoint_run(T0, Ci, gTnt, gT0, gCi, workspace, ckpt_ready: bool, lam, dt, rdx, rdy, rdz, nt: int,
+                ckpt_every: int) -> None:
+    """Reverse sweep: gT0 = dL/dT0 and gCi = dL/dCi from gTnt = dL/dT_nt."""
+    _field(T0, "T0")
+    for name, t in (("Ci", Ci), ("gTnt", gTnt), ("gT0", gT0), ("gCi", gCi)):
+        _field(t, name, T0)
+    nz, ny, nx = T0.shape
+    _check(_lib.diff3d_adjoint_run(_p(T0), _p(Ci), _p(gTnt), _p(gT0), _p(gCi), _p(workspace),
+                                   workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                   int(bool(ckpt_ready)), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nt),
+                                   int(ckpt_every), _code(T0), _stream(T0)), "adjoint_run")
+
+
+def loss(T: torch.Tensor, Tt: torch.Tensor, seed: torch.Tensor | None = None) -> torch.Tensor:
+    """0.5*||T - Tt||^2 accumulated in FP64 on the GPU (0-d float64 tensor);
+    writes T - Tt into ``seed`` when given."""
+    _field(T, "T")
+    _field(Tt, "Tt", T)
+    if seed is not None:
+        _field(seed, "seed", T)
+    acc = _acc(T.device)
+    _check(_lib.diff3d_loss(_p(T), _p(Tt), _p(seed), T.numel(), _code(T), _p(acc), _stream(T)), "loss")
+    return acc[0]
+
+
+def norm2(x: torch.Tensor) -> torch.Tensor:
+    """||x||^2 accumulated in FP64 on the GPU (0-d float64 tensor)."""
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous GPU tensor")
+    acc = _acc(x.device)
+    _check(_lib.diff3d_norm2(_p(x), x.numel(), _code(x), _p(acc), _stream(x)), "norm2")
+    return acc[0]
+
+
+def copy_(dst: torch.Tensor, src: torch.Tensor) -> None:
+    """Device copy through the library's streaming copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst too small")
+    _check(_lib.diff3d_copy(_p(dst), _p(src), nbytes, _stream(src)), "copy")
+
+
+class Diffuse3D(torch.autograd.Function):
+    """T_nt = nt steps of the Fig. 1 scheme from T0 with Ci; differentiable in
+    T0 and Ci through the library's checkpointed reverse sweep (a checkpoint
+    every ``ckpt_every`` steps, recomputation in between)."""
+
+    @staticmethod
+    def forward(ctx, T0, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt_every):
+        if T0.dtype not in (torch.float64, torch.float32):
+            raise TypeError("gradients are supported for float64 and float32 fields")
+        T0 = T0.contiguous()
+        Ci = Ci.contiguous()
+        T = T0.clone()
+        T2 = torch.empty_like(T0)
+        ws_bytes = adjoint_workspace_bytes(T0.shape, nt, ckpt_every, T0.dtype)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=T0.device)
+        run(T, T2, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt=ws, ckpt_every=ckpt_every)
+        ctx.save_for_backward(T0, Ci)
+        ctx.ws = ws
+        ctx.args = (lam, dt, rdx, rdy, rdz, int(nt), int(ckpt_every))
+        return T
+
+    @staticmethod
+    def backward(ctx, gT):
+        T0, Ci = ctx.saved_tensors
+        lam, dt, rdx, rdy, rdz, nt, ce = ctx.args
+        gT = gT.contiguous()
+        gT0 = torch.empty_like(T0)
+        gCi = torch.empty_like(Ci)
+        adjoint_run(T0, Ci, gT, gT0, gCi, ctx.ws, True, lam, dt, rdx, rdy, rdz, nt, ce)
+        ctx.ws = None
+        return gT0, gCi, None, None, None, None, None, None, None
+
+
+def diffuse(T0, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt_every=None):
+    """Differentiable nt-step diffusion; ckpt_every defaults to about sqrt(nt)."""
+    if ckpt_every is None:
+        ckpt_every = max(1, int(round(nt ** 0.5)))
+    return Diffuse3D.apply(T0, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt_every)

@@ -1,0 +1,575 @@
+// C ABI of the diff3d library: argument validation, kernel selection and
+// launch, the time loop with the buffer swap, and the checkpointed reverse
+// sweep.  Everything is enqueued on the caller's stream; no device memory is
+// allocated here.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "adjoint_kernels.hpp"
+#include "common.hpp"
+#include "diff3d.h"
+#include "step_kernels.hpp"
+#include "util_kernels.hpp"
+
+using namespace diff3d;
+
+namespace {
+
+int g_kernel = DIFF3D_KERNEL_AUTO;
+uint64_t g_sr_seed = 0x5EEDu;
+uint64_t g_sr_step = 0;
+
+constexpr size_t kMaxPoints = (size_t)1 << 40;
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int hip_status()
+{
+    return hipGetLastError() == hipSuccess ? DIFF3D_OK : DIFF3D_EHIP;
+}
+
+inline bool known_dtype(int dt) { return dt >= DIFF3D_F64 && dt <= DIFF3D_BF16_RNE; }
+
+inline size_t elem_size(int dt)
+{
+    switch (dt) {
+    case DIFF3D_F64: return 8;
+    case DIFF3D_F32: return 4;
+    case DIFF3D_BF16:
+    case DIFF3D_BF16_RNE: return 2;
+    default: return 0;
+    }
+}
+
+int check_grid(int nx, int ny, int nz)
+{
+    if (nx < 3 || ny < 3 || nz < 3) return DIFF3D_EINVAL;
+    if ((size_t)nx * (size_t)ny * (size_t)nz >= kMaxPoints) return DIFF3D_EINVAL;
+    return DIFF3D_OK;
+}
+
+inline size_t npoints(int nx, int ny, int nz) { return (size_t)nx * ny * nz; }
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+inline bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+int env_int(const char* name, int dflt)
+{
+    const char* s = getenv(name);
+    if (!s || !*s) return dflt;
+    return atoi(s);
+}
+
+// ------------------------------------------------------------------ forward
+template <int DT>
+StepArgs<DT> make_step_args(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
+                            double rdx, double rdy, double rdz, uint64_t step_index)
+{
+    using S = typename Traits<DT>::S;
+    using C = typename Traits<DT>::C;
+    StepArgs<DT> a;
+    a.T2 = static_cast<S*>(T2);
+    a.T = static_cast<const S*>(T);
+    a.Ci = static_cast<const S*>(Ci);
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.lam = (C)lam;
+    a.dt = (C)dt;
+    a.cx = (C)(rdx * rdx);
+    a.cy = (C)(rdy * rdy);
+    a.cz = (C)(rdz * rdz);
+    a.sr.k0 = (uint32_t)g_sr_seed;
+    a.sr.k1 = (uint32_t)(g_sr_seed >> 32);
+    a.sr.s0 = (uint32_t)step_index;
+    a.sr.s1 = (uint32_t)(step_index >> 32);
+    return a;
+}
+
+template <int DT>
+int launch_naive(const StepArgs<DT>& a, hipStream_t st)
+{
+    dim3 grid((unsigned)((a.nx - 2 + 63) / 64), (unsigned)((a.ny - 2 + 3) / 4), (unsigned)min(a.nz - 2, 65535));
+    step_naive<DT><<<grid, 256, 0, st>>>(a);
+    return hip_status();
+}
+
+// z-march tile configurations: rows per thread R and waves per workgroup NW
+struct ZPlan {
+    int ntx, nty, zlen, nchunks;
+    unsigned blocks;
+};
+
+inline ZPlan plan_tiles(int nx, int ny, int nzout, int TX, int TY, int zlen_req)
+{
+    ZPlan p;
+    p.ntx = (nx + TX - 1) / TX;
+    p.nty = (ny + TY - 1) / TY;
+    const long tiles = (long)p.ntx * p.nty;
+    int zlen = zlen_req;
+    if (zlen <= 0) {
+        // enough workgroups to fill 256 CUs several times over, but keep the
+        // two extra planes a chunk reads small against its length
+        const long want = 4096;
+        long nch = (want + tiles - 1) / tiles;
+        if (nch < 1) nch = 1;
+        zlen = (int)((nzout + nch - 1) / nch);
+        if (zlen < 16) zlen = 16;
+    }
+    if (zlen > nzout) zlen = nzout;
+    p.zlen = zlen;
+    p.nchunks = (nzout + zlen - 1) / zlen;
+    p.blocks = (unsigned)(tiles * p.nchunks);
+    return p;
+}
+
+template <int DT, int V, int R, int NW>
+int launch_zmarch_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req)
+{
+    const ZPlan p = plan_tiles(a.nx, a.ny, a.nz - 2, 64 * V, R * NW, zlen_req);
+    step_zmarch<DT, V, R, NW><<<p.blocks, 64 * NW, 0, st>>>(a, p.ntx, p.nty, p.zlen);
+    return hip_status();
+}
+
+template <int DT, int V>
+int launch_zmarch_v(const StepArgs<DT>& a, hipStream_t st, int cfg, int zlen)
+{
+    switch (cfg) {
+    case 1: return launch_zmarch_cfg<DT, V, 2, 4>(a, st, zlen);
+    case 2: return launch_zmarch_cfg<DT, V, 8, 4>(a, st, zlen);
+    case 3: return launch_zmarch_cfg<DT, V, 4, 8>(a, st, zlen);
+    case 4: return launch_zmarch_cfg<DT, V, 2, 8>(a, st, zlen);
+    default: return launch_zmarch_cfg<DT, V, 4, 4>(a, st, zlen);
+    }
+}
+
+template <int DT>
+int launch_zmarch(const StepArgs<DT>& a, hipStream_t st)
+{
+    using S = typename Traits<DT>::S;
+    constexpr int VW = 16 / sizeof(S);
+    const int cfg = env_int("DIFF3D_ZCFG", 0);
+    const int zlen = env_int("DIFF3D_ZLEN", 0);
+    const int narrow = env_int("DIFF3D_NARROW", 0);
+    const bool wide = !narrow && a.nx % VW == 0 && ((uintptr_t)a.T % 16 == 0) && ((uintptr_t)a.T2 % 16 == 0) &&
+                      ((uintptr_t)a.Ci % 16 == 0);
+    if (wide) return launch_zmarch_v<DT, VW>(a, st, cfg, zlen);
+    return launch_zmarch_v<DT, 1>(a, st, cfg, zlen);
+}
+
+template <int DT>
+int launch_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
+                double rdy, double rdz, uint64_t step_index, hipStream_t st)
+{
+    const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index);
+    if (g_kernel == DIFF3D_KERNEL_NAIVE) return launch_naive<DT>(a, st);
+    return launch_zmarch<DT>(a, st);
+}
+
+int step_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
+                  double rdx, double rdy, double rdz, uint64_t step_index, hipStream_t st)
+{
+    switch (dtype) {
+    case DIFF3D_F64: return launch_step<DIFF3D_F64>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    case DIFF3D_F32: return launch_step<DIFF3D_F32>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    case DIFF3D_BF16: return launch_step<DIFF3D_BF16>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    case DIFF3D_BF16_RNE:
+        return launch_step<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    default: return DIFF3D_EDTYPE;
+    }
+}
+
+// ------------------------------------------------------------------ helpers
+int copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return DIFF3D_OK;
+    if ((uintptr_t)dst % 16 || (uintptr_t)src % 16) {
+        // fields are at least 2-byte aligned: move 16-bit words
+        const size_t n2 = bytes / 2;
+        size_t blocks = (n2 + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        copy_u16<<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint16_t*>(dst), static_cast<const uint16_t*>(src), n2);
+        return hip_status();
+    }
+    const size_t n16 = bytes / 16, tail = bytes % 16;
+    if (n16) {
+        size_t blocks = (n16 + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        copy16<<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint4*>(dst), static_cast<const uint4*>(src), n16);
+    }
+    if (tail)
+        copy_tail<<<1, 64, 0, st>>>(static_cast<unsigned char*>(dst) + n16 * 16,
+                                    static_cast<const unsigned char*>(src) + n16 * 16, tail);
+    return hip_status();
+}
+
+int zero_bytes(void* p, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return DIFF3D_OK;
+    const size_t n16 = bytes / 16, tail = bytes % 16;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 8192) blocks = 8192;
+    fill_zero<<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint4*>(p), n16,
+                                                 static_cast<unsigned char*>(p) + n16 * 16, tail);
+    return hip_status();
+}
+
+int boundary_dispatch(int dtype, void* dst, const void* src, int nx, int ny, int nz, hipStream_t st)
+{
+    const size_t total = 2 * ((size_t)nx * ny + (size_t)nx * nz + (size_t)ny * nz);
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    switch (elem_size(dtype)) {
+    case 8:
+        boundary_copy<uint64_t><<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint64_t*>(dst),
+                                                                   static_cast<const uint64_t*>(src), nx, ny, nz);
+        break;
+    case 4:
+        boundary_copy<uint32_t><<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint32_t*>(dst),
+                                                                   static_cast<const uint32_t*>(src), nx, ny, nz);
+        break;
+    case 2:
+        boundary_copy<uint16_t><<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint16_t*>(dst),
+                                                                   static_cast<const uint16_t*>(src), nx, ny, nz);
+        break;
+    default: return DIFF3D_EDTYPE;
+    }
+    return hip_status();
+}
+
+// The time loop of Fig. 1 on two buffers; checkpoint field j-1 receives
+// T_{j*C} for every j >= 1 with j*C <= klast.  With want_result the final
+// state is left in T.
+int run_loop(int dtype, void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
+             double rdy, double rdz, int nt, hipStream_t st, void* ckpt, int C, size_t field_stride, int klast,
+             bool want_result)
+{
+    int rc = boundary_dispatch(dtype, T2, T, nx, ny, nz, st);
+    if (rc) return rc;
+    const size_t fbytes = npoints(nx, ny, nz) * elem_size(dtype);
+    void* a = T;
+    void* b = T2;
+    for (int it = 0; it < nt; ++it) {
+        rc = step_dispatch(dtype, b, a, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step + (uint64_t)it, st);
+        if (rc) return rc;
+        void* s = a;
+        a = b;
+        b = s;
+        const int k = it + 1;
+        if (ckpt && k % C == 0 && k <= klast) {
+            rc = copy_bytes(static_cast<char*>(ckpt) + (size_t)(k / C - 1) * field_stride, a, fbytes, st);
+            if (rc) return rc;
+        }
+    }
+    g_sr_step += (uint64_t)nt;
+    if (want_result && a != T) return copy_bytes(T, a, fbytes, st);
+    return DIFF3D_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+template <int DT>
+AdjArgs<DT> make_adj_args(void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny,
+                          int nz, double lam, double dt, double rdx, double rdy, double rdz)
+{
+    using S = typename Traits<DT>::S;
+    using C = typename Traits<DT>::C;
+    AdjArgs<DT> a;
+    a.lout = static_cast<S*>(lout);
+    a.lin = static_cast<const S*>(lin);
+    a.Ci = static_cast<const S*>(Ci);
+    a.Tk = static_cast<const S*>(Tk);
+    a.gCi = static_cast<S*>(gCi);
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.dtlam = (C)dt * (C)lam;
+    a.cx = (C)(rdx * rdx);
+    a.cy = (C)(rdy * rdy);
+    a.cz = (C)(rdz * rdz);
+    return a;
+}
+
+template <int DT, int V, int R, int NW>
+int launch_adj_cfg(const AdjArgs<DT>& a, hipStream_t st, int zlen_req)
+{
+    const ZPlan p = plan_tiles(a.nx, a.ny, a.nz, 64 * V, R * NW, zlen_req);
+    adj_zmarch<DT, V, R, NW><<<p.blocks, 64 * NW, 0, st>>>(a, p.ntx, p.nty, p.zlen);
+    return hip_status();
+}
+
+template <int DT>
+int launch_adj(void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny, int nz,
+               double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+{
+    using S = typename Traits<DT>::S;
+    constexpr int VW = 16 / sizeof(S);
+    const AdjArgs<DT> a = make_adj_args<DT>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz);
+    if (g_kernel == DIFF3D_KERNEL_NAIVE) {
+        dim3 grid((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4), (unsigned)min(nz, 65535));
+        adj_naive<DT><<<grid, 256, 0, st>>>(a);
+        return hip_status();
+    }
+    const int zlen = env_int("DIFF3D_AZLEN", 0);
+    const bool wide = !env_int("DIFF3D_NARROW", 0) && nx % VW == 0 && (uintptr_t)lout % 16 == 0 &&
+                      (uintptr_t)lin % 16 == 0 && (uintptr_t)Ci % 16 == 0 && (uintptr_t)Tk % 16 == 0 &&
+                      (uintptr_t)gCi % 16 == 0;
+    if (wide) return launch_adj_cfg<DT, VW, 4, 4>(a, st, zlen);
+    return launch_adj_cfg<DT, 1, 4, 4>(a, st, zlen);
+}
+
+int adj_dispatch(int dtype, void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny,
+                 int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+{
+    switch (dtype) {
+    case DIFF3D_F64: return launch_adj<DIFF3D_F64>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    case DIFF3D_F32: return launch_adj<DIFF3D_F32>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    default: return DIFF3D_EDTYPE;
+    }
+}
+
+inline int nck_of(int nt, int C) { return nt > 0 ? (nt + C - 1) / C : 0; }
+
+// ------------------------------------------------------------------ reductions
+template <int DT, int OP>
+int reduce_launch(const void* x, const void* y, void* seed, size_t n, double* acc, hipStream_t st)
+{
+    using S = typename Traits<DT>::S;
+    size_t parts = (n + 255) / 256;
+    if (parts > (size_t)kRedParts) parts = kRedParts;
+    if (parts < 1) parts = 1;
+    reduce_partial<DT, OP><<<(unsigned)parts, 256, 0, st>>>(static_cast<const S*>(x), static_cast<const S*>(y),
+                                                            static_cast<S*>(seed), n, acc);
+    reduce_final<OP><<<1, 1024, 0, st>>>(acc, (int)parts);
+    return hip_status();
+}
+
+template <int OP>
+int reduce_dispatch(int dtype, const void* x, const void* y, void* seed, size_t n, double* acc, hipStream_t st)
+{
+    switch (dtype) {
+    case DIFF3D_F64: return reduce_launch<DIFF3D_F64, OP>(x, y, seed, n, acc, st);
+    case DIFF3D_F32: return reduce_launch<DIFF3D_F32, OP>(x, y, seed, n, acc, st);
+    case DIFF3D_BF16:
+    case DIFF3D_BF16_RNE: return reduce_launch<DIFF3D_BF16_RNE, OP>(x, y, seed, n, acc, st);
+    default: return DIFF3D_EDTYPE;
+    }
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* diff3d_strerror(int status)
+{
+    switch (status) {
+    case DIFF3D_OK: return "ok";
+    case DIFF3D_EINVAL: return "invalid argument (pointer, size, count or aliasing)";
+    case DIFF3D_EDTYPE: return "unsupported dtype";
+    case DIFF3D_EWORKSPACE: return "workspace missing or too small";
+    case DIFF3D_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+size_t diff3d_dtype_size(int dtype) { return elem_size(dtype); }
+
+const char* diff3d_version(void) { return "diff3d 0.1 gfx950"; }
+
+int diff3d_scalars(int nx, int ny, int nz, double lx, double ly, double lz, double lam, double cimax, double* out)
+{
+    if (!out || check_grid(nx, ny, nz)) return DIFF3D_EINVAL;
+    if (!(lam > 0.0) || !(cimax > 0.0) || !(lx > 0.0) || !(ly > 0.0) || !(lz > 0.0)) return DIFF3D_EINVAL;
+    const double dx = lx / (nx - 1), dy = ly / (ny - 1), dz = lz / (nz - 1);
+    double m = dx * dx;
+    if (dy * dy < m) m = dy * dy;
+    if (dz * dz < m) m = dz * dz;
+    out[0] = dx;
+    out[1] = dy;
+    out[2] = dz;
+    out[3] = 1.0 / dx;
+    out[4] = 1.0 / dy;
+    out[5] = 1.0 / dz;
+    out[6] = m / lam / cimax / 6.1;
+    return DIFF3D_OK;
+}
+
+int diff3d_max(const void* x, size_t n, int dtype, double* acc, void* stream)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (!x || !acc || n == 0) return DIFF3D_EINVAL;
+    return reduce_dispatch<RED_MAX>(dtype, x, nullptr, nullptr, n, acc, as_stream(stream));
+}
+
+int diff3d_loss(const void* T, const void* Tt, void* seed, size_t n, int dtype, double* acc, void* stream)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (!T || !Tt || !acc || n == 0) return DIFF3D_EINVAL;
+    return reduce_dispatch<RED_SUMSQ_DIFF>(dtype, T, Tt, seed, n, acc, as_stream(stream));
+}
+
+int diff3d_norm2(const void* x, size_t n, int dtype, double* acc, void* stream)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (!x || !acc || n == 0) return DIFF3D_EINVAL;
+    return reduce_dispatch<RED_SUMSQ>(dtype, x, nullptr, nullptr, n, acc, as_stream(stream));
+}
+
+int diff3d_copy(void* dst, const void* src, size_t bytes, void* stream)
+{
+    if (bytes == 0) return DIFF3D_OK;
+    if (!dst || !src || overlap(dst, bytes, src, bytes)) return DIFF3D_EINVAL;
+    if ((uintptr_t)dst % 16 || (uintptr_t)src % 16) return DIFF3D_EINVAL;
+    return copy_bytes(dst, src, bytes, as_stream(stream));
+}
+
+int diff3d_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
+                double rdy, double rdz, int dtype, void* stream)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (!T2 || !T || !Ci || check_grid(nx, ny, nz)) return DIFF3D_EINVAL;
+    const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
+    if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb)) return DIFF3D_EINVAL;
+    const int rc = step_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step, as_stream(stream));
+    g_sr_step += 1;
+    return rc;
+}
+
+int diff3d_run(void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
+               double rdy, double rdz, int nt, int dtype, void* stream, void* ckpt, int ckpt_every)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (!T || !T2 || !Ci || check_grid(nx, ny, nz) || nt < 0) return DIFF3D_EINVAL;
+    if (ckpt && ckpt_every < 1) return DIFF3D_EINVAL;
+    const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
+    if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb) || overlap(T, fb, Ci, fb)) return DIFF3D_EINVAL;
+    const size_t stride = align256(fb);
+    if (ckpt) {
+        const int nck = nck_of(nt, ckpt_every);
+        const size_t cb = nck > 1 ? (size_t)(nck - 1) * stride : 0;
+        if (cb && (overlap(ckpt, cb, T, fb) || overlap(ckpt, cb, T2, fb) || overlap(ckpt, cb, Ci, fb)))
+            return DIFF3D_EINVAL;
+    }
+    if (nt == 0) return DIFF3D_OK;
+    return run_loop(dtype, T, T2, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nt, as_stream(stream), ckpt, ckpt_every,
+                    stride, nt - 1, true);
+}
+
+size_t diff3d_adjoint_workspace_bytes(int nx, int ny, int nz, int nt, int ckpt_every, int dtype)
+{
+    if (!known_dtype(dtype) || check_grid(nx, ny, nz) || nt < 0 || ckpt_every < 1) return 0;
+    const size_t stride = align256(npoints(nx, ny, nz) * elem_size(dtype));
+    const int nck = nck_of(nt, ckpt_every);
+    const size_t fields = (size_t)(nck > 1 ? nck - 1 : 0) + (size_t)(ckpt_every - 1) + 1;
+    return fields * stride;
+}
+
+int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* gT0, void* gCi, void* workspace,
+                       size_t ws_bytes, int ckpt_ready, int nx, int ny, int nz, double lam, double dt, double rdx,
+                       double rdy, double rdz, int nt, int ckpt_every, int dtype, void* stream)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (dtype != DIFF3D_F64 && dtype != DIFF3D_F32) return DIFF3D_EDTYPE;
+    if (!T0 || !Ci || !gTnt || !gT0 || !gCi || check_grid(nx, ny, nz) || nt < 0 || ckpt_every < 1)
+        return DIFF3D_EINVAL;
+    const size_t need = diff3d_adjoint_workspace_bytes(nx, ny, nz, nt, ckpt_every, dtype);
+    if (!workspace || ws_bytes < need) return DIFF3D_EWORKSPACE;
+    const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
+    const void* ins[3] = {T0, Ci, gTnt};
+    void* outs[2] = {gT0, gCi};
+    for (int o = 0; o < 2; ++o) {
+        for (int i = 0; i < 3; ++i)
+            if (overlap(outs[o], fb, ins[i], fb)) return DIFF3D_EINVAL;
+        if (overlap(outs[o], fb, workspace, need)) return DIFF3D_EINVAL;
+    }
+    if (overlap(gT0, fb, gCi, fb)) return DIFF3D_EINVAL;
+    for (int i = 0; i < 3; ++i)
+        if (overlap(workspace, need, ins[i], fb)) return DIFF3D_EINVAL;
+
+    hipStream_t st = as_stream(stream);
+    const int C = ckpt_every;
+    const size_t stride = align256(fb);
+    char* ws = static_cast<char*>(workspace);
+    const int nck = nck_of(nt, C);
+    auto slot = [&](int j) -> void* { return ws + (size_t)(j - 1) * stride; };   // T_{jC}, j >= 1
+    char* seg0 = ws + (size_t)(nck > 1 ? nck - 1 : 0) * stride;                  // C-1 recompute fields
+    auto seg = [&](int i) -> void* { return seg0 + (size_t)i * stride; };
+    void* W = seg0 + (size_t)(C - 1) * stride;                                   // adjoint ping-pong
+
+    int rc = zero_bytes(gCi, fb, st);
+    if (rc) return rc;
+    if (nt == 0) return copy_bytes(gT0, gTnt, fb, st);
+
+    if (!ckpt_ready && nck > 1) {
+        // forward from T0 on the two scratch fields W and gT0, filling the slots
+        rc = copy_bytes(W, T0, fb, st);
+        const int last = (nck - 1) * C;
+        if (!rc) rc = run_loop(dtype, W, gT0, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, last, st, ws, C, stride, last,
+                               false);
+        if (rc) return rc;
+    }
+    // recompute fields need T0's boundary (steps write interior points only)
+    const int segn = (C - 1 < nt - 1 ? C - 1 : nt - 1);
+    for (int i = 0; i < segn; ++i) {
+        rc = boundary_dispatch(dtype, seg(i), T0, nx, ny, nz, st);
+        if (rc) return rc;
+    }
+
+    const void* lin = gTnt;
+    for (int j = nck - 1; j >= 0; --j) {
+        const int s = j * C;
+        const int e = (s + C < nt) ? s + C : nt;
+        const void* base = j == 0 ? T0 : slot(j);
+        // states T_{s+1} .. T_{e-1} into seg(0) .. seg(e-s-2)
+        const void* src = base;
+        for (int k = s; k < e - 1; ++k) {
+            rc = step_dispatch(dtype, seg(k - s), src, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, 0, st);
+            if (rc) return rc;
+            src = seg(k - s);
+        }
+        for (int k = e - 1; k >= s; --k) {
+            const void* Tk = k == s ? base : seg(k - s - 1);
+            void* out = (k % 2 == 0) ? gT0 : W;
+            rc = adj_dispatch(dtype, out, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+            if (rc) return rc;
+            lin = out;
+        }
+    }
+    return DIFF3D_OK;
+}
+
+int diff3d_set_kernel(int kernel)
+{
+    if (kernel < DIFF3D_KERNEL_AUTO || kernel > DIFF3D_KERNEL_ZMARCH) return DIFF3D_EINVAL;
+    g_kernel = kernel;
+    return DIFF3D_OK;
+}
+
+int diff3d_get_kernel(void) { return g_kernel; }
+
+void diff3d_set_sr_seed(uint64_t seed, uint64_t step0)
+{
+    g_sr_seed = seed;
+    g_sr_step = step0;
+}
+
+void diff3d_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const u32x4 r = philox4x32_10(u32x4{ctr[0], ctr[1], ctr[2], ctr[3]}, key[0], key[1]);
+    out[0] = r.x;
+    out[1] = r.y;
+    out[2] = r.z;
+    out[3] = r.w;
+}
+
+}  // extern "C"

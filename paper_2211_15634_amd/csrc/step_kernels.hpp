@@ -1,0 +1,240 @@
+// Forward time-step kernels of the explicit 3-D heat-diffusion scheme
+// (Fig. 1, `step!`): on interior points
+//   T2 = T + dt*((lam*Ci)*((d2x*cx + d2y*cy) + d2z*cz)),
+//   d2x = (T[x+1] - T[x]) - (T[x] - T[x-1])  (likewise y, z),
+// evaluated in this order with no contraction (the library is built with
+// -ffp-contract=off), so the FP64 form reproduces a plain loop bit for bit.
+#pragma once
+
+#include "common.hpp"
+
+namespace diff3d {
+
+template <int DT>
+struct StepArgs {
+    using S = typename Traits<DT>::S;
+    using C = typename Traits<DT>::C;
+    S* __restrict__ T2;
+    const S* __restrict__ T;
+    const S* __restrict__ Ci;
+    int nx, ny, nz;
+    C lam, dt, cx, cy, cz;
+    SrState sr;
+};
+
+template <int DT>
+__device__ inline typename Traits<DT>::C stencil_point(typename Traits<DT>::C t, typename Traits<DT>::C xm,
+                                                       typename Traits<DT>::C xp, typename Traits<DT>::C ym,
+                                                       typename Traits<DT>::C yp, typename Traits<DT>::C zm,
+                                                       typename Traits<DT>::C zp, typename Traits<DT>::C ci,
+                                                       const StepArgs<DT>& a)
+{
+    using C = typename Traits<DT>::C;
+    const C d2x = (xp - t) - (t - xm);
+    const C d2y = (yp - t) - (t - ym);
+    const C d2z = (zp - t) - (t - zm);
+    return t + a.dt * ((a.lam * ci) * ((d2x * a.cx + d2y * a.cy) + d2z * a.cz));
+}
+
+// ------------------------------------------------------------------ naive
+// One thread per interior point; the seven reads of T go through the
+// caches.  Block 64 x 4 over (x, y); grid z strides over interior planes.
+template <int DT>
+__global__ __launch_bounds__(256) void step_naive(StepArgs<DT> a)
+{
+    using Tr = Traits<DT>;
+    using C = typename Tr::C;
+    const int ix = blockIdx.x * 64 + (threadIdx.x & 63) + 1;
+    const int iy = blockIdx.y * 4 + (threadIdx.x >> 6) + 1;
+    if (ix > a.nx - 2 || iy > a.ny - 2) return;
+    const size_t sy = (size_t)a.nx, sz = (size_t)a.nx * a.ny;
+    for (int iz = blockIdx.z + 1; iz < a.nz - 1; iz += gridDim.z) {
+        const size_t i = (size_t)ix + sy * iy + sz * iz;
+        const C t = Tr::load(a.T[i]);
+        const C r = stencil_point<DT>(t, Tr::load(a.T[i - 1]), Tr::load(a.T[i + 1]), Tr::load(a.T[i - sy]),
+                                      Tr::load(a.T[i + sy]), Tr::load(a.T[i - sz]), Tr::load(a.T[i + sz]),
+                                      Tr::load(a.Ci[i]), a);
+        uint32_t rnd = 0;
+        if (Tr::sr) rnd = sr_pick(sr_block(a.sr, i >> 3), (unsigned)(i & 7));
+        a.T2[i] = Tr::store(r, rnd);
+    }
+}
+
+// ------------------------------------------------------------------ z-march
+// A workgroup of NW wave64s owns an x-y tile of TX = 64*V by TY = R*NW
+// points and marches along z over `zlen` output planes.  Lane l of wave w
+// holds V consecutive x points (one 16-byte load when V > 1) of the R
+// consecutive rows y0 + w*R .. y0 + w*R + R-1.
+//  - z neighbours: three planes (z-1, z, z+1) of the thread's points live in
+//    registers, and the plane z+2 is loaded one iteration ahead;
+//  - x and y neighbours inside the thread come from registers, the others
+//    from the current plane staged in LDS (double-buffered, one LDS-only
+//    barrier per plane); halo rows and columns of the tile are loaded by
+//    designated waves;
+//  - each element of T and Ci is read from HBM about once per step (halo
+//    re-reads of neighbouring tiles are L2 hits when they share an XCD).
+template <int DT, int V, int R, int NW>
+__global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, int nty, int zlen)
+{
+    using Tr = Traits<DT>;
+    using S = typename Tr::S;
+    using C = typename Tr::C;
+    constexpr int TX = 64 * V, TY = R * NW, LW = TX + 2;
+    constexpr int WYL = 0, WYH = NW - 1;
+    constexpr int WXL = NW >= 3 ? 1 : 0, WXR = NW >= 4 ? 2 : NW - 1;
+    static_assert(TY <= 64, "x-halo columns are loaded by one lane per row");
+    __shared__ C lds[2][TY + 2][LW];
+
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = (int)(t % (unsigned)ntx);
+    const int rest = (int)(t / (unsigned)ntx);
+    const int ty = rest % nty, tz = rest / nty;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int zb = 1 + tz * zlen;
+    const int ze = min(nz - 1, zb + zlen);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int xl = x0 + lane * V;
+    const bool xin = xl < nx;            // nx % V == 0: a vector is wholly in or out
+    const int yw = y0 + wave * R;        // first row of this thread
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+
+    C prev[R][V], cur[R][V], nxt[R][V], nn[R][V], ci[R][V], ci2[R][V];
+    C hyl[V], hyh[V], hxl = C(0), hxr = C(0);        // halo of plane z+1
+    C nyl[V], nyh[V], nxl = C(0), nxr = C(0);        // halo of plane z+2
+
+    auto load_rows = [&](const S* base, int z, C (&dst)[R][V]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (xin && yw + r < ny) {
+                S raw[V];
+                vload<S, V>(base + (size_t)xl + sy * (yw + r) + sz * z, raw);
+#pragma unroll
+                for (int v = 0; v < V; ++v) dst[r][v] = Tr::load(raw[v]);
+            }
+        }
+    };
+    auto load_halo = [&](int z, C (&yl)[V], C (&yh)[V], C& xlo, C& xhi) {
+        if (wave == WYL && xin && y0 >= 1) {
+            S raw[V];
+            vload<S, V>(a.T + (size_t)xl + sy * (y0 - 1) + sz * z, raw);
+#pragma unroll
+            for (int v = 0; v < V; ++v) yl[v] = Tr::load(raw[v]);
+        }
+        if (wave == WYH && xin && y0 + TY < ny) {
+            S raw[V];
+            vload<S, V>(a.T + (size_t)xl + sy * (y0 + TY) + sz * z, raw);
+#pragma unroll
+            for (int v = 0; v < V; ++v) yh[v] = Tr::load(raw[v]);
+        }
+        if (wave == WXL && lane < TY && y0 + lane < ny && x0 >= 1)
+            xlo = Tr::load(a.T[(size_t)(x0 - 1) + sy * (y0 + lane) + sz * z]);
+        if (wave == WXR && lane < TY && y0 + lane < ny && x0 + TX < nx)
+            xhi = Tr::load(a.T[(size_t)(x0 + TX) + sy * (y0 + lane) + sz * z]);
+    };
+    auto stage = [&](int buf, const C (&c)[R][V], const C (&yl)[V], const C (&yh)[V], C xlo, C xhi) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < V; ++v) lds[buf][1 + wave * R + r][1 + lane * V + v] = c[r][v];
+        if (wave == WYL)
+#pragma unroll
+            for (int v = 0; v < V; ++v) lds[buf][0][1 + lane * V + v] = yl[v];
+        if (wave == WYH)
+#pragma unroll
+            for (int v = 0; v < V; ++v) lds[buf][TY + 1][1 + lane * V + v] = yh[v];
+        if (wave == WXL && lane < TY) lds[buf][1 + lane][0] = xlo;
+        if (wave == WXR && lane < TY) lds[buf][1 + lane][TX + 1] = xhi;
+    };
+
+    // prologue: planes zb-1, zb (staged), zb+1 (+ halo) and Ci at zb
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            prev[r][v] = cur[r][v] = nxt[r][v] = nn[r][v] = ci[r][v] = ci2[r][v] = C(0);
+        }
+#pragma unroll
+    for (int v = 0; v < V; ++v) hyl[v] = hyh[v] = nyl[v] = nyh[v] = C(0);
+    load_rows(a.T, zb - 1, prev);
+    load_rows(a.T, zb, cur);
+    {
+        C yl[V], yh[V], xlo = C(0), xhi = C(0);
+#pragma unroll
+        for (int v = 0; v < V; ++v) yl[v] = yh[v] = C(0);
+        load_halo(zb, yl, yh, xlo, xhi);
+        stage(0, cur, yl, yh, xlo, xhi);
+    }
+    load_rows(a.T, zb + 1, nxt);
+    load_halo(zb + 1, hyl, hyh, hxl, hxr);
+    load_rows(a.Ci, zb, ci);
+
+    int b = 0;
+    for (int z = zb; z < ze; ++z) {
+        const bool more = z + 1 < ze;
+        if (more) {
+            load_rows(a.T, z + 2, nn);
+            load_halo(z + 2, nyl, nyh, nxl, nxr);
+            load_rows(a.Ci, z + 1, ci2);
+        }
+        lds_barrier();
+        if (more) stage(b ^ 1, nxt, hyl, hyh, hxl, hxr);
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = yw + r;
+            if (!(xin && y >= 1 && y <= ny - 2)) continue;
+            const int row = 1 + wave * R + r;
+            C out[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int col = 1 + lane * V + v;
+                const C xm = v > 0 ? cur[r][v - 1] : lds[b][row][col - 1];
+                const C xp = v < V - 1 ? cur[r][v + 1] : lds[b][row][col + 1];
+                const C ym = r > 0 ? cur[r - 1][v] : lds[b][row - 1][col];
+                const C yp = r < R - 1 ? cur[r + 1][v] : lds[b][row + 1][col];
+                out[v] = stencil_point<DT>(cur[r][v], xm, xp, ym, yp, prev[r][v], nxt[r][v], ci[r][v], a);
+            }
+            const size_t i0 = (size_t)xl + sy * y + sz * z;
+            uint32_t rnd[V];
+            if (Tr::sr) {
+                const u32x4 rb = sr_block(a.sr, i0 >> 3);
+#pragma unroll
+                for (int v = 0; v < V; ++v) rnd[v] = sr_pick(rb, (unsigned)((i0 + v) & 7));
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) rnd[v] = 0;
+            }
+            S st[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) st[v] = Tr::store(out[v], rnd[v]);
+            if (xl >= 1 && xl + V - 1 <= nx - 2) {
+                vstore<S, V>(a.T2 + i0, st);
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (xl + v >= 1 && xl + v <= nx - 2) a.T2[i0 + v] = st[v];
+            }
+        }
+
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                prev[r][v] = cur[r][v];
+                cur[r][v] = nxt[r][v];
+                nxt[r][v] = nn[r][v];
+                ci[r][v] = ci2[r][v];
+            }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            hyl[v] = nyl[v];
+            hyh[v] = nyh[v];
+        }
+        hxl = nxl;
+        hxr = nxr;
+        b ^= 1;
+    }
+}
+
+}  // namespace diff3d

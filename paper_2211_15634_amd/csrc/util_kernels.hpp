@@ -1,0 +1,136 @@
+// Support kernels: boundary copy (T2 = T on the boundary, as T2 = copy(T)
+// in Fig. 1), zero fill, the bandwidth-reference copy and deterministic FP64
+// reductions (max, loss, squared norm).
+#pragma once
+
+#include "common.hpp"
+
+namespace diff3d {
+
+// dst = src on the six faces of an nx*ny*nz grid (edges are written twice
+// with the same value).
+template <class S>
+__global__ __launch_bounds__(256) void boundary_copy(S* __restrict__ dst, const S* __restrict__ src, int nx,
+                                                     int ny, int nz)
+{
+    const size_t fz = (size_t)nx * ny, fy = (size_t)nx * nz, fx = (size_t)ny * nz;
+    const size_t total = 2 * (fz + fy + fx);
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < total; k += (size_t)gridDim.x * 256) {
+        size_t i;
+        size_t q = k;
+        if (q < 2 * fz) {                      // z = 0 and z = nz-1
+            const size_t side = q / fz, r = q % fz;
+            i = r + sz * (side ? (size_t)(nz - 1) : 0);
+        } else if ((q -= 2 * fz) < 2 * fy) {   // y = 0 and y = ny-1
+            const size_t side = q / fy, r = q % fy;
+            const size_t x = r % nx, z = r / nx;
+            i = x + sy * (side ? (size_t)(ny - 1) : 0) + sz * z;
+        } else {                               // x = 0 and x = nx-1
+            q -= 2 * fy;
+            const size_t side = q / fx, r = q % fx;
+            const size_t y = r % ny, z = r / ny;
+            i = (side ? (size_t)(nx - 1) : 0) + sy * y + sz * z;
+        }
+        dst[i] = src[i];
+    }
+}
+
+__global__ __launch_bounds__(256) void fill_zero(uint4* __restrict__ p, size_t n16, unsigned char* __restrict__ tail,
+                                                 size_t ntail)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+// Streaming copy, four 16-byte vectors in flight per thread per iteration.
+__global__ __launch_bounds__(256) void copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n16)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void copy_u16(uint16_t* __restrict__ dst, const uint16_t* __restrict__ src,
+                                                size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+__global__ void copy_tail(unsigned char* __restrict__ dst, const unsigned char* __restrict__ src, size_t n)
+{
+    if (threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+// ------------------------------------------------------------------ reductions
+// Pass 1: block b reduces a fixed grid-stride subset into acc[1 + b]
+// (fixed tree in LDS); pass 2: one block reduces acc[1 .. nparts] into
+// acc[0].  Same grid and same order on every call: deterministic.
+enum { RED_MAX = 0, RED_SUMSQ_DIFF = 1, RED_SUMSQ = 2 };
+constexpr int kRedParts = 1024;
+
+template <int DT, int OP>
+__global__ __launch_bounds__(256) void reduce_partial(const typename Traits<DT>::S* __restrict__ x,
+                                                      const typename Traits<DT>::S* __restrict__ y,
+                                                      typename Traits<DT>::S* __restrict__ seed, size_t n,
+                                                      double* __restrict__ acc)
+{
+    using Tr = Traits<DT>;
+    __shared__ double sh[256];
+    double s = OP == RED_MAX ? -__builtin_huge_val() : 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const double v = (double)Tr::load(x[i]);
+        if (OP == RED_MAX) {
+            s = v > s ? v : s;
+        } else if (OP == RED_SUMSQ) {
+            s += v * v;
+        } else {
+            const double r = v - (double)Tr::load(y[i]);
+            if (seed) {
+                // RNE for every storage form (the reverse sweep runs in FP64/FP32)
+                if (sizeof(typename Tr::S) == 2)
+                    seed[i] = (typename Tr::S)f32_to_bf16_rne((float)r);
+                else
+                    seed[i] = (typename Tr::S)r;
+            }
+            s += r * r;
+        }
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double o = sh[threadIdx.x + w];
+            sh[threadIdx.x] = OP == RED_MAX ? (o > sh[threadIdx.x] ? o : sh[threadIdx.x]) : sh[threadIdx.x] + o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[1 + blockIdx.x] = sh[0];
+}
+
+template <int OP>
+__global__ __launch_bounds__(1024) void reduce_final(double* __restrict__ acc, int nparts)
+{
+    __shared__ double sh[1024];
+    const double id = OP == RED_MAX ? -__builtin_huge_val() : 0.0;
+    sh[threadIdx.x] = (int)threadIdx.x < nparts ? acc[1 + threadIdx.x] : id;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double o = sh[threadIdx.x + w];
+            sh[threadIdx.x] = OP == RED_MAX ? (o > sh[threadIdx.x] ? o : sh[threadIdx.x]) : sh[threadIdx.x] + o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[0] = OP == RED_SUMSQ_DIFF ? 0.5 * sh[0] : sh[0];
+}
+
+}  // namespace diff3d

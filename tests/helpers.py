@@ -1,0 +1,84 @@
+"""Shared test helpers: moving seeded numpy fields to the GPU, sub-box
+oracle evaluation at sampled points, and error measures."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+
+def to_dev(a: np.ndarray, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def to_host(t) -> np.ndarray:
+    import torch
+    return t.detach().to(dtype=torch.float64).cpu().numpy()
+
+
+def interior_mask(shape):
+    m = np.zeros(shape, bool)
+    m[1:-1, 1:-1, 1:-1] = True
+    return m
+
+
+def max_rel(a: np.ndarray, b: np.ndarray) -> float:
+    """max_i |a_i - b_i| / |b_i| (b is the reference; floor 1e-300)."""
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def norm_rel(a: np.ndarray, b: np.ndarray) -> float:
+    """max|a - b| / max|b|."""
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def box(point, radius, shape):
+    """Index slices of the box of the given radius around point, clipped to
+    the grid, and the point's position inside it."""
+    sl, pos = [], []
+    for p, n in zip(point, shape):
+        lo, hi = max(0, p - radius), min(n, p + radius + 1)
+        sl.append(slice(lo, hi))
+        pos.append(p - lo)
+    return tuple(sl), tuple(pos)
+
+
+def oracle_forward_at(T0, Ci, s, nt, points):
+    """T_nt at the given (iz, iy, ix) points from the oracle run on the box of
+    radius nt around each point.  The box faces that are not domain faces are
+    held at T0, which is wrong from step 1 on; the error travels one cell per
+    step, so the centre, nt cells from those faces, is exact after nt steps
+    (the same floating-point operations on the same values as a full run)."""
+    out = []
+    for p in points:
+        sl, pos = box(p, max(nt, 2), T0.shape)
+        T = oracle.forward(T0[sl], Ci[sl], s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
+        out.append(T[pos])
+    return np.array(out)
+
+
+def oracle_reverse_at(T0, Ci, g, s, nt, points, keep=1):
+    """(gT0, gCi) at the given points from the oracle reverse sweep on the box
+    of radius nt+1 around each point: within nt steps the adjoint at the
+    centre only sees points at distance <= nt, and the forward states it uses
+    (centre and neighbours) are exact for the same reason as above."""
+    a, b = [], []
+    for p in points:
+        sl, pos = box(p, max(nt + 1, 2), T0.shape)
+        gT0, gCi = oracle.reverse(T0[sl], Ci[sl], g[sl], s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt,
+                                  keep=keep)
+        a.append(gT0[pos])
+        b.append(gCi[pos])
+    return np.array(a), np.array(b)
+
+
+def sample_points(shape, rng, k, include_edges=True):
+    nz, ny, nx = shape
+    pts = []
+    if include_edges:
+        pts += [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (1, 1, 1), (nz - 2, ny - 2, nx - 2), (0, ny // 2, nx // 2),
+                (nz // 2, ny - 1, nx // 3), (nz // 3, 1, nx - 1)]
+    for _ in range(k):
+        pts.append((int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))))
+    return pts

@@ -1,0 +1,171 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+the header declares, rejects bad arguments on the host before enqueueing
+anything, and its host-side arithmetic (scalars, Philox) is right."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "diff3d.h")
+
+d3 = pytest.importorskip("paper_2211_15634_amd")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(diff3d_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(d3.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(d3.EXPORTS)
+
+
+def test_strerror_and_sizes():
+    for code in (d3.OK, d3.EINVAL, d3.EDTYPE, d3.EWORKSPACE, d3.EHIP):
+        assert d3.strerror(code) and d3.strerror(code) != "unknown status"
+    assert d3.strerror(12345) == "unknown status"
+    lib = d3._lib
+    assert [lib.diff3d_dtype_size(i) for i in range(5)] == [8, 4, 2, 2, 0]
+    assert "gfx950" in d3.version()
+
+
+def test_scalars_match_oracle_bitwise():
+    for (nx, ny, nz, lx, ly, lz, lam) in [(64, 64, 64, 1, 1, 1, 1.0), (512, 512, 512, 1, 1, 1, 1.0),
+                                          (9, 6, 11, 2.0, 0.5, 3.0, 2.0), (33, 17, 5, 1.0, 1.3, 0.7, 0.5)]:
+        Ci = 0.5 * (1.0 + 0.5 * workloads.uniform(min(nx, 40), min(ny, 40), min(nz, 40), 1))
+        cimax = float(Ci.max())
+        # the oracle computes max(Ci) itself; give it a field with the same maximum
+        full = np.full((nz, ny, nx), cimax)
+        a = oracle.scalars(nx, ny, nz, full, lam=lam, lx=lx, ly=ly, lz=lz)
+        b = d3.scalars(nx, ny, nz, cimax, lam=lam, lx=lx, ly=ly, lz=lz)
+        for k in ("dx", "dy", "dz", "rdx", "rdy", "rdz", "dt"):
+            assert a[k] == b[k], k
+
+
+def test_scalars_reject():
+    with pytest.raises(d3.Diff3dError):
+        d3.scalars(2, 5, 5, 0.5)
+    with pytest.raises(d3.Diff3dError):
+        d3.scalars(5, 5, 5, 0.0)
+    with pytest.raises(d3.Diff3dError):
+        d3.scalars(5, 5, 5, 0.5, lam=-1.0)
+
+
+def test_philox_known_answers():
+    # Known-answer vectors of Philox4x32-10 published with the Random123 library
+    assert d3.philox4x32_10((0, 0, 0, 0), (0, 0)) == (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)
+    f = 0xFFFFFFFF
+    assert d3.philox4x32_10((f, f, f, f), (f, f)) == (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)
+    assert d3.philox4x32_10((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0)) == \
+        (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)
+
+
+def test_workspace_bytes():
+    f = 64 * 64 * 64 * 8
+    # nt=200, C=14: 15 checkpoints (14 stored), 13 recompute fields, 1 ping-pong
+    assert d3._lib.diff3d_adjoint_workspace_bytes(64, 64, 64, 200, 14, d3.F64) == (14 + 13 + 1) * f
+    # nt=500, C=32 at 1024^3 FP32: 16 checkpoints
+    g = 1024 ** 3 * 4
+    assert d3._lib.diff3d_adjoint_workspace_bytes(1024, 1024, 1024, 500, 32, d3.F32) == (15 + 31 + 1) * g
+    assert d3._lib.diff3d_adjoint_workspace_bytes(64, 64, 64, 0, 14, d3.F64) == 14 * f
+    assert d3._lib.diff3d_adjoint_workspace_bytes(64, 64, 64, 10, 0, d3.F64) == 0
+    assert d3._lib.diff3d_adjoint_workspace_bytes(2, 64, 64, 10, 3, d3.F64) == 0
+    assert d3._lib.diff3d_adjoint_workspace_bytes(64, 64, 64, 10, 3, 9) == 0
+    # ragged field sizes are padded to 256-byte boundaries
+    r = 5 * 6 * 7 * 4
+    assert d3._lib.diff3d_adjoint_workspace_bytes(5, 6, 7, 10, 3, d3.F32) == (3 + 2 + 1) * ((r + 255) // 256 * 256)
+
+
+# Host-side validation: every call below must be rejected before any HIP
+# call, so it is safe without a GPU.  Fake non-null addresses are never
+# dereferenced on these paths.
+P = ctypes.c_void_p
+A, B, Cc = P(0x10000000), P(0x20000000), P(0x30000000)
+
+
+def test_step_validation():
+    L = d3._lib
+    args = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
+    assert L.diff3d_step(None, B, Cc, *args, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_step(A, None, Cc, *args, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_step(A, B, None, *args, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_step(A, B, Cc, *args, 7, None) == d3.EDTYPE
+    assert L.diff3d_step(A, B, Cc, *args, -1, None) == d3.EDTYPE
+    assert L.diff3d_step(A, A, Cc, *args, d3.F64, None) == d3.EINVAL      # T2 aliases T
+    assert L.diff3d_step(A, B, A, *args, d3.F64, None) == d3.EINVAL       # T2 aliases Ci
+    # T2 overlapping the tail of T
+    near = P(0x20000000 + 64 * 64 * 64 * 8 - 8)
+    assert L.diff3d_step(near, B, Cc, *args, d3.F64, None) == d3.EINVAL
+    for bad in ((2, 64, 64), (64, 2, 64), (64, 64, 2), (0, 5, 5), (-5, 5, 5)):
+        assert L.diff3d_step(A, B, Cc, *bad, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F64, None) == d3.EINVAL
+    # more than 2^40 points
+    assert L.diff3d_step(A, B, Cc, 1 << 14, 1 << 14, 1 << 14, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F32, None) == d3.EINVAL
+
+
+def test_run_validation():
+    L = d3._lib
+    g = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
+    assert L.diff3d_run(A, B, Cc, *g, -1, d3.F64, None, None, 0) == d3.EINVAL
+    assert L.diff3d_run(A, B, Cc, *g, 10, 5, None, None, 0) == d3.EDTYPE
+    assert L.diff3d_run(A, A, Cc, *g, 10, d3.F64, None, None, 0) == d3.EINVAL
+    assert L.diff3d_run(A, B, A, *g, 10, d3.F64, None, None, 0) == d3.EINVAL
+    assert L.diff3d_run(A, B, Cc, *g, 10, d3.F64, None, P(0x40000000), 0) == d3.EINVAL  # ckpt without C
+    assert L.diff3d_run(A, B, Cc, *g, 30, d3.F64, None, A, 10) == d3.EINVAL             # ckpt over T
+    assert L.diff3d_run(A, B, Cc, *g, 0, d3.F64, None, None, 0) == d3.OK                # nt=0: no-op
+
+
+def test_adjoint_validation():
+    L = d3._lib
+    W = P(0x50000000)
+    n = 32 * 32 * 32 * 8
+    ws = L.diff3d_adjoint_workspace_bytes(32, 32, 32, 20, 5, d3.F64)
+    g = (32, 32, 32, 1.0, 1e-4, 31.0, 31.0, 31.0, 20, 5)
+    D, E = P(0x60000000), P(0x70000000)
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws, 0, *g, d3.BF16, None) == d3.EDTYPE
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws, 0, *g, 9, None) == d3.EDTYPE
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws - 1, 0, *g, d3.F64, None) == d3.EWORKSPACE
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, None, ws, 0, *g, d3.F64, None) == d3.EWORKSPACE
+    assert L.diff3d_adjoint_run(A, B, Cc, D, D, W, ws, 0, *g, d3.F64, None) == d3.EINVAL   # gT0 == gCi
+    assert L.diff3d_adjoint_run(A, B, Cc, A, E, W, ws, 0, *g, d3.F64, None) == d3.EINVAL   # gT0 == T0
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, P(0x60000000 + n // 2), ws, 0, *g, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_adjoint_run(None, B, Cc, D, E, W, ws, 0, *g, d3.F64, None) == d3.EINVAL
+    bad = (32, 32, 32, 1.0, 1e-4, 31.0, 31.0, 31.0, 20, 0)
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws, 0, *bad, d3.F64, None) == d3.EINVAL
+
+
+def test_reduction_and_copy_validation():
+    L = d3._lib
+    assert L.diff3d_max(None, 10, d3.F64, A, None) == d3.EINVAL
+    assert L.diff3d_max(A, 0, d3.F64, B, None) == d3.EINVAL
+    assert L.diff3d_max(A, 10, 8, B, None) == d3.EDTYPE
+    assert L.diff3d_loss(A, None, None, 10, d3.F64, B, None) == d3.EINVAL
+    assert L.diff3d_loss(A, B, None, 10, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_norm2(A, 10, 11, B, None) == d3.EDTYPE
+    assert L.diff3d_copy(A, A, 64, None) == d3.EINVAL
+    assert L.diff3d_copy(A, P(0x10000008), 64, None) == d3.EINVAL     # overlap
+    assert L.diff3d_copy(P(0x10000004), B, 64, None) == d3.EINVAL     # misaligned
+    assert L.diff3d_copy(A, B, 0, None) == d3.OK
+
+
+def test_kernel_selection_roundtrip():
+    old = d3.get_kernel()
+    try:
+        for k in (d3.KERNEL_NAIVE, d3.KERNEL_ZMARCH, d3.KERNEL_AUTO):
+            d3.set_kernel(k)
+            assert d3.get_kernel() == k
+        with pytest.raises(d3.Diff3dError):
+            d3.set_kernel(17)
+    finally:
+        d3.set_kernel(old)

@@ -1,0 +1,231 @@
+"""Forward step and time loop on the GPU against the oracle.
+
+The FP64 kernels evaluate the step in the oracle's operation order with no
+contraction, so FP64 results must be bit-identical to the oracle's."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from helpers import interior_mask, oracle_forward_at, sample_points, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SHAPES = [  # (nz, ny, nx): several tiles, ragged tails, minimal grids
+    (7, 9, 131),      # nx odd: narrow (V=1) path
+    (21, 37, 128),    # wide vectors, ragged y tile
+    (40, 66, 256),
+    (3, 3, 3),        # a single interior point
+    (5, 3, 64),
+    (18, 70, 70),     # nx % 16 != 0 for bf16/fp32 wide vectors
+]
+
+
+@pytest.fixture(autouse=True)
+def _reset(lib):
+    saved = {k: os.environ.get(k) for k in ("DIFF3D_ZCFG", "DIFF3D_ZLEN", "DIFF3D_NARROW")}
+    lib.set_kernel(lib.KERNEL_AUTO)
+    yield
+    lib.set_kernel(lib.KERNEL_AUTO)
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
+def _inputs(shape, seed=0):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(100 + seed)
+    T0 = rng.random(shape)
+    Ci = 0.5 * (1.0 + 0.5 * rng.random(shape))
+    s = oracle.scalars(nx, ny, nz, Ci, ly=1.3, lz=0.8)
+    return T0, Ci, s
+
+
+def _gpu_run(lib, T0, Ci, s, nt, dtype=torch.float64, rounding="sr"):
+    T = to_dev(T0, dtype)
+    T2 = torch.empty_like(T)
+    C = to_dev(Ci, dtype)
+    lib.run(T, T2, C, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt, rounding=rounding)
+    torch.cuda.synchronize()
+    return T, T2
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("kernel", ["naive", "zmarch"])
+def test_fp64_bit_exact(lib, shape, kernel):
+    lib.set_kernel(lib.KERNEL_NAIVE if kernel == "naive" else lib.KERNEL_ZMARCH)
+    T0, Ci, s = _inputs(shape)
+    for nt in (1, 6, 7):
+        ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
+        T, _ = _gpu_run(lib, T0, Ci, s, nt)
+        np.testing.assert_array_equal(to_host(T), ref)
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("zlen", [0, 1, 3, 5])
+@pytest.mark.parametrize("narrow", [0, 1])
+def test_fp64_tilings_bit_exact(lib, cfg, zlen, narrow):
+    os.environ["DIFF3D_ZCFG"] = str(cfg)
+    os.environ["DIFF3D_ZLEN"] = str(zlen)
+    os.environ["DIFF3D_NARROW"] = str(narrow)
+    lib.set_kernel(lib.KERNEL_ZMARCH)
+    shape = (13, 45, 192)
+    T0, Ci, s = _inputs(shape, seed=cfg)
+    ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 4)
+    T, _ = _gpu_run(lib, T0, Ci, s, 4)
+    np.testing.assert_array_equal(to_host(T), ref)
+
+
+def test_uniform64_config_bit_exact(lib):
+    """64^3 FP64, T0 ~ U[0,1] (seed 0), Ci = 0.5, dt by the 6.1 rule, nt = 100."""
+    T0, Ci = workloads.uniform_const(64, 64, 64)
+    s = oracle.scalars(64, 64, 64, Ci)
+    ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 100)
+    T, _ = _gpu_run(lib, T0, Ci, s, 100)
+    np.testing.assert_array_equal(to_host(T), ref)
+
+
+def test_scalars_from_device_max(lib):
+    T0, Ci = workloads.bump(48, 40, 36)
+    a = oracle.scalars(48, 40, 36, Ci)
+    b = lib.problem_scalars(to_dev(Ci, torch.float64))
+    assert a == b
+    # max over the whole array, boundary included
+    Ci2 = Ci.copy()
+    Ci2[-1, -1, -1] = 3.0
+    assert float(lib.field_max(to_dev(Ci2, torch.float64))) == 3.0
+    assert float(lib.field_max(to_dev(Ci2, torch.float32))) == 3.0
+
+
+def test_step_sentinels(lib):
+    """One step writes every interior point and no boundary point of T2."""
+    for kernel in (lib.KERNEL_NAIVE, lib.KERNEL_ZMARCH):
+        lib.set_kernel(kernel)
+        for shape in ((9, 17, 130), (12, 20, 128)):
+            T0, Ci, s = _inputs(shape)
+            for dt_ in (torch.float64, torch.float32, torch.bfloat16):
+                T = to_dev(T0, dt_)
+                C = to_dev(Ci, dt_)
+                T2 = torch.full_like(T, float("nan"))
+                m = torch.from_numpy(~interior_mask(shape)).cuda()
+                T2[m] = -7.0
+                lib.step(T2, T, C, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+                torch.cuda.synchronize()
+                h = to_host(T2)
+                assert np.all(np.isfinite(h[interior_mask(shape)]))
+                assert np.all(h[~interior_mask(shape)] == -7.0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "bf16_rne"])
+def test_constant_field_kept_exactly(lib, dtype):
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "bf16_rne": torch.bfloat16}[dtype]
+    shape = (20, 33, 256)
+    _, Ci, s = _inputs(shape)
+    T0 = np.full(shape, 1.7)
+    T, _ = _gpu_run(lib, T0, Ci, s, 9, dtype=tdt, rounding="rne" if dtype == "bf16_rne" else "sr")
+    c = to_dev(T0, tdt)
+    assert torch.equal(T, c)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "bf16_rne"])
+@pytest.mark.parametrize("shape", [(11, 19, 133), (16, 40, 256)])
+def test_kernels_agree_bitwise(lib, dtype, shape):
+    """naive and z-march kernels give identical bits (same operation order;
+    the same Philox draw for every point under stochastic rounding)."""
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "bf16_rne": torch.bfloat16}[dtype]
+    rounding = "rne" if dtype == "bf16_rne" else "sr"
+    T0, Ci, s = _inputs(shape)
+    outs = []
+    for kernel in (lib.KERNEL_NAIVE, lib.KERNEL_ZMARCH):
+        lib.set_kernel(kernel)
+        lib.set_sr_seed(1234, 0)
+        T, _ = _gpu_run(lib, T0, Ci, s, 5, dtype=tdt, rounding=rounding)
+        outs.append(T)
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_deterministic_and_seeded(lib):
+    shape = (24, 48, 128)
+    T0, Ci, s = _inputs(shape)
+    for tdt in (torch.float64, torch.float32, torch.bfloat16):
+        lib.set_sr_seed(99, 0)
+        a, _ = _gpu_run(lib, T0, Ci, s, 8, dtype=tdt)
+        lib.set_sr_seed(99, 0)
+        b, _ = _gpu_run(lib, T0, Ci, s, 8, dtype=tdt)
+        assert torch.equal(a, b)
+    # a different seed changes stochastic rounding somewhere
+    lib.set_sr_seed(100, 0)
+    c, _ = _gpu_run(lib, T0, Ci, s, 8, dtype=torch.bfloat16)
+    assert not torch.equal(a, c)
+
+
+def test_run_semantics(lib):
+    shape = (10, 12, 64)
+    T0, Ci, s = _inputs(shape)
+    # nt = 0 leaves T alone
+    T, _ = _gpu_run(lib, T0, Ci, s, 0)
+    np.testing.assert_array_equal(to_host(T), T0)
+    # odd nt: the result is still in T; T2's boundary was set from T
+    T, T2 = _gpu_run(lib, T0, Ci, s, 3)
+    ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 3)
+    np.testing.assert_array_equal(to_host(T), ref)
+    b = ~interior_mask(shape)
+    np.testing.assert_array_equal(to_host(T2)[b], T0[b])
+    # run(nt=1) equals a single step on a copy
+    Td = to_dev(T0, torch.float64)
+    T2d = Td.clone()
+    lib.step(T2d, Td, to_dev(Ci, torch.float64), s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+    T1, _ = _gpu_run(lib, T0, Ci, s, 1)
+    assert torch.equal(T1, T2d)
+
+
+def test_checkpoints_written(lib):
+    shape = (12, 14, 64)
+    T0, Ci, s = _inputs(shape)
+    nt, C = 23, 5
+    ws = torch.zeros(lib.adjoint_workspace_bytes(shape, nt, C, torch.float64), dtype=torch.uint8, device="cuda")
+    T = to_dev(T0, torch.float64)
+    T2 = torch.empty_like(T)
+    lib.run(T, T2, to_dev(Ci, torch.float64), s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt, ckpt=ws,
+            ckpt_every=C)
+    torch.cuda.synchronize()
+    stride = (T.numel() * 8 + 255) // 256 * 256
+    for j in range(1, (nt + C - 1) // C):
+        field = ws[(j - 1) * stride:(j - 1) * stride + T.numel() * 8].view(torch.float64).reshape(shape)
+        ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], j * C)
+        np.testing.assert_array_equal(to_host(field), ref)
+
+
+def test_copy_kernel(lib):
+    for n in (1, 15, 16, 17, 4096 + 3, 1 << 20):
+        src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros_like(src)
+        lib.copy_(dst, src)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+
+
+def test_bump512_sampled_bit_exact(lib):
+    """512^3 FP64 bump workload, nt = 100, in the launch configuration the
+    benchmark uses; sampled points against the oracle on sub-boxes."""
+    n = 512
+    T0, Ci = workloads.bump(n, n, n)
+    s = oracle.scalars(n, n, n, Ci)
+    T, _ = _gpu_run(lib, T0, Ci, s, 100)
+    got = to_host(T)
+    del T
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(5)
+    pts = sample_points(T0.shape, rng, 3)
+    ref = oracle_forward_at(T0, Ci, s, 100, pts)
+    np.testing.assert_array_equal(np.array([got[p] for p in pts]), ref)
+    # properties at full size: boundary untouched, bounded by the data range
+    b = ~interior_mask(T0.shape)
+    assert np.array_equal(got[b], T0[b])
+    assert got.min() >= T0.min() and got.max() <= T0.max()
