@@ -184,8 +184,15 @@ def run(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: flo
     _field(T2, "T2", T)
     _field(Ci, "Ci", T)
     nz, ny, nx = T.shape
-    if ckpt is not None and (not ckpt.is_cuda or not ckpt.is_contiguous()):
-        raise ValueError("ckpt must be a contiguous GPU buffer")
+    if ckpt is not None:
+        if not ckpt.is_cuda or not ckpt.is_contiguous():
+            raise ValueError("ckpt must be a contiguous GPU buffer")
+        if ckpt_every < 1:
+            raise ValueError("ckpt_every must be >= 1 with a checkpoint buffer")
+        nck = (nt + ckpt_every - 1) // ckpt_every if nt > 0 else 0
+        stride = (T.numel() * T.element_size() + 255) // 256 * 256
+        if ckpt.numel() * ckpt.element_size() < max(nck - 1, 0) * stride:
+            raise ValueError("ckpt buffer too small for %d checkpoints" % max(nck - 1, 0))
     _check(_lib.diff3d_run(_p(T), _p(T2), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nt), _code(T, rounding),
                            _stream(T), _p(ckpt), int(ckpt_every)), "run")
 
