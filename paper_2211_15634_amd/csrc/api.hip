@@ -6,6 +6,7 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -103,13 +104,18 @@ int launch_naive(const StepArgs<DT>& a, hipStream_t st)
     return hip_status();
 }
 
-// z-march tile configurations: rows per thread R and waves per workgroup NW
+// z-march launch plan: tiles of TX x TY over x-y, chunks of zlen planes along z
 struct ZPlan {
     int ntx, nty, zlen, nchunks;
     unsigned blocks;
 };
 
-inline ZPlan plan_tiles(int nx, int ny, int nzout, int TX, int TY, int zlen_req)
+// zdef: preferred planes per chunk (long chunks amortise the two extra
+// planes a chunk reads); the chunk is shortened until the launch has at
+// least kMinBlocks workgroups.
+constexpr long kMinBlocks = 512;
+
+inline ZPlan plan_tiles(int nx, int ny, int nzout, int TX, int TY, int zlen_req, int zdef)
 {
     ZPlan p;
     p.ntx = (nx + TX - 1) / TX;
@@ -117,13 +123,11 @@ inline ZPlan plan_tiles(int nx, int ny, int nzout, int TX, int TY, int zlen_req)
     const long tiles = (long)p.ntx * p.nty;
     int zlen = zlen_req;
     if (zlen <= 0) {
-        // enough workgroups to fill 256 CUs several times over, but keep the
-        // two extra planes a chunk reads small against its length
-        const long want = 4096;
-        long nch = (want + tiles - 1) / tiles;
-        if (nch < 1) nch = 1;
+        long nch = (nzout + zdef - 1) / zdef;
+        const long need = (kMinBlocks + tiles - 1) / tiles;
+        if (nch < need) nch = need;
         zlen = (int)((nzout + nch - 1) / nch);
-        if (zlen < 16) zlen = 16;
+        if (zlen < 4) zlen = 4;
     }
     if (zlen > nzout) zlen = nzout;
     p.zlen = zlen;
@@ -132,38 +136,82 @@ inline ZPlan plan_tiles(int nx, int ny, int nzout, int TX, int TY, int zlen_req)
     return p;
 }
 
-template <int DT, int V, int R, int NW>
-int launch_zmarch_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req)
+// A tile configuration: V points per lane along x, R rows per thread, NW
+// waves per workgroup, NT non-temporal stream accesses.
+struct ZKey {
+    int V, R, NW, NT;
+};
+
+inline bool key_eq(const ZKey& a, int V, int R, int NW, int NT)
 {
-    const ZPlan p = plan_tiles(a.nx, a.ny, a.nz - 2, 64 * V, R * NW, zlen_req);
-    step_zmarch<DT, V, R, NW><<<p.blocks, 64 * NW, 0, st>>>(a, p.ntx, p.nty, p.zlen);
+    return a.V == V && a.R == R && a.NW == NW && a.NT == NT;
+}
+
+// Configuration override "V,R,NW[,NT]" from the environment (tuning only).
+inline bool env_key(const char* name, ZKey& k)
+{
+    const char* s = getenv(name);
+    if (!s || !*s) return false;
+    ZKey r{0, 0, 0, 0};
+    const int got = sscanf(s, "%d,%d,%d,%d", &r.V, &r.R, &r.NW, &r.NT);
+    if (got < 3) return false;
+    if (got == 3) r.NT = 0;
+    k = r;
+    return true;
+}
+
+// Instantiated forward configurations per storage size (V*sizeof(S) <= 16).
+#define DIFF3D_FWD_CFGS_8(X) X(1, 4, 4, 0) X(1, 8, 4, 0) X(1, 4, 8, 0) X(2, 4, 4, 0) X(2, 8, 4, 0) X(2, 2, 8, 0) \
+    X(2, 4, 8, 0) X(2, 4, 4, 1) X(2, 8, 4, 1) X(2, 4, 8, 1)
+#define DIFF3D_FWD_CFGS_4(X) X(1, 4, 4, 0) X(2, 4, 4, 0) X(2, 8, 4, 0) X(2, 4, 8, 0) X(4, 2, 4, 0) X(4, 4, 4, 0) \
+    X(4, 2, 8, 0) X(4, 2, 8, 1) X(4, 4, 4, 1) X(2, 8, 4, 1)
+#define DIFF3D_FWD_CFGS_2(X) X(1, 4, 4, 0) X(2, 4, 4, 0) X(2, 8, 4, 0) X(4, 2, 4, 0) X(4, 4, 4, 0) X(4, 2, 8, 0) \
+    X(4, 1, 8, 0) X(8, 1, 8, 0) X(8, 2, 4, 0) X(4, 4, 4, 1) X(2, 8, 4, 1) X(4, 2, 8, 1)
+
+template <int DT>
+struct FwdDefaults;
+template <> struct FwdDefaults<DIFF3D_F64> { static constexpr ZKey wide{2, 4, 4, 1}; static constexpr int zdef = 128; };
+template <> struct FwdDefaults<DIFF3D_F32> { static constexpr ZKey wide{4, 4, 4, 1}; static constexpr int zdef = 32; };
+template <> struct FwdDefaults<DIFF3D_BF16> { static constexpr ZKey wide{4, 1, 8, 0}; static constexpr int zdef = 16; };
+template <> struct FwdDefaults<DIFF3D_BF16_RNE> { static constexpr ZKey wide{4, 2, 8, 1}; static constexpr int zdef = 64; };
+constexpr ZKey kNarrow{1, 4, 4, 0};
+
+template <int DT, int V, int R, int NW, int NT>
+int launch_zmarch_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req, int zdef)
+{
+    const ZPlan p = plan_tiles(a.nx, a.ny, a.nz - 2, 64 * V, R * NW, zlen_req, zdef);
+    step_zmarch<DT, V, R, NW, NT != 0><<<p.blocks, 64 * NW, 0, st>>>(a, p.ntx, p.nty, p.zlen);
     return hip_status();
 }
 
-template <int DT, int V>
-int launch_zmarch_v(const StepArgs<DT>& a, hipStream_t st, int cfg, int zlen)
+// Vector width V is usable when rows start on V-element boundaries and all
+// three fields are 16-byte aligned.
+template <class S>
+inline bool vec_ok(int nx, int V, const void* p0, const void* p1, const void* p2)
 {
-    switch (cfg) {
-    case 1: return launch_zmarch_cfg<DT, V, 2, 4>(a, st, zlen);
-    case 2: return launch_zmarch_cfg<DT, V, 8, 4>(a, st, zlen);
-    case 3: return launch_zmarch_cfg<DT, V, 4, 8>(a, st, zlen);
-    case 4: return launch_zmarch_cfg<DT, V, 2, 8>(a, st, zlen);
-    default: return launch_zmarch_cfg<DT, V, 4, 4>(a, st, zlen);
-    }
+    return V == 1 || (nx % V == 0 && (uintptr_t)p0 % 16 == 0 && (uintptr_t)p1 % 16 == 0 && (uintptr_t)p2 % 16 == 0);
 }
 
 template <int DT>
 int launch_zmarch(const StepArgs<DT>& a, hipStream_t st)
 {
     using S = typename Traits<DT>::S;
-    constexpr int VW = 16 / sizeof(S);
-    const int cfg = env_int("DIFF3D_ZCFG", 0);
+    ZKey k = FwdDefaults<DT>::wide;
+    env_key("DIFF3D_ZCFG", k);
+    if (env_int("DIFF3D_NARROW", 0) || !vec_ok<S>(a.nx, k.V, a.T, a.T2, a.Ci)) k = kNarrow;
     const int zlen = env_int("DIFF3D_ZLEN", 0);
-    const int narrow = env_int("DIFF3D_NARROW", 0);
-    const bool wide = !narrow && a.nx % VW == 0 && ((uintptr_t)a.T % 16 == 0) && ((uintptr_t)a.T2 % 16 == 0) &&
-                      ((uintptr_t)a.Ci % 16 == 0);
-    if (wide) return launch_zmarch_v<DT, VW>(a, st, cfg, zlen);
-    return launch_zmarch_v<DT, 1>(a, st, cfg, zlen);
+    const int zdef = FwdDefaults<DT>::zdef;
+#define DIFF3D_TRY(v, r, nw, nt) \
+    if (key_eq(k, v, r, nw, nt)) return launch_zmarch_cfg<DT, v, r, nw, nt>(a, st, zlen, zdef);
+    if constexpr (sizeof(S) == 8) {
+        DIFF3D_FWD_CFGS_8(DIFF3D_TRY)
+    } else if constexpr (sizeof(S) == 4) {
+        DIFF3D_FWD_CFGS_4(DIFF3D_TRY)
+    } else {
+        DIFF3D_FWD_CFGS_2(DIFF3D_TRY)
+    }
+#undef DIFF3D_TRY
+    return DIFF3D_EINVAL;   // configuration not instantiated (tuning override only)
 }
 
 template <int DT>
@@ -202,9 +250,9 @@ int copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t st)
     }
     const size_t n16 = bytes / 16, tail = bytes % 16;
     if (n16) {
-        size_t blocks = (n16 + 255) / 256;
-        if (blocks > 8192) blocks = 8192;
-        copy16<<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint4*>(dst), static_cast<const uint4*>(src), n16);
+        const size_t per = 256 * kCopyUnroll;
+        const size_t blocks = (n16 + per - 1) / per;   // < 2^31 for any field below 2^40 points
+        copy16<<<(unsigned)blocks, 256, 0, st>>>(static_cast<u32v4*>(dst), static_cast<const u32v4*>(src), n16);
     }
     if (tail)
         copy_tail<<<1, 64, 0, st>>>(static_cast<unsigned char*>(dst) + n16 * 16,
@@ -299,10 +347,18 @@ AdjArgs<DT> make_adj_args(void* lout, const void* lin, const void* Ci, const voi
     return a;
 }
 
+#define DIFF3D_ADJ_CFGS_8(X) X(1, 4, 4) X(1, 2, 4) X(1, 2, 8) X(1, 4, 8) X(2, 2, 4) X(2, 1, 8) X(2, 2, 8)
+#define DIFF3D_ADJ_CFGS_4(X) X(1, 4, 4) X(1, 2, 4) X(1, 2, 8) X(2, 2, 4) X(2, 2, 8) X(4, 1, 4) X(4, 1, 8) X(2, 1, 8)
+
+template <int DT>
+struct AdjDefaults;
+template <> struct AdjDefaults<DIFF3D_F64> { static constexpr ZKey wide{2, 1, 8, 0}; static constexpr int zdef = 32; };
+template <> struct AdjDefaults<DIFF3D_F32> { static constexpr ZKey wide{4, 1, 8, 0}; static constexpr int zdef = 16; };
+
 template <int DT, int V, int R, int NW>
-int launch_adj_cfg(const AdjArgs<DT>& a, hipStream_t st, int zlen_req)
+int launch_adj_cfg(const AdjArgs<DT>& a, hipStream_t st, int zlen_req, int zdef)
 {
-    const ZPlan p = plan_tiles(a.nx, a.ny, a.nz, 64 * V, R * NW, zlen_req);
+    const ZPlan p = plan_tiles(a.nx, a.ny, a.nz, 64 * V, R * NW, zlen_req, zdef);
     adj_zmarch<DT, V, R, NW><<<p.blocks, 64 * NW, 0, st>>>(a, p.ntx, p.nty, p.zlen);
     return hip_status();
 }
@@ -312,19 +368,28 @@ int launch_adj(void* lout, const void* lin, const void* Ci, const void* Tk, void
                double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
 {
     using S = typename Traits<DT>::S;
-    constexpr int VW = 16 / sizeof(S);
     const AdjArgs<DT> a = make_adj_args<DT>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz);
     if (g_kernel == DIFF3D_KERNEL_NAIVE) {
         dim3 grid((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4), (unsigned)min(nz, 65535));
         adj_naive<DT><<<grid, 256, 0, st>>>(a);
         return hip_status();
     }
+    ZKey k = AdjDefaults<DT>::wide;
+    env_key("DIFF3D_ACFG", k);
+    const bool aligned = (uintptr_t)lout % 16 == 0 && (uintptr_t)lin % 16 == 0 && (uintptr_t)Ci % 16 == 0 &&
+                         (uintptr_t)Tk % 16 == 0 && (uintptr_t)gCi % 16 == 0;
+    if (k.V > 1 && (env_int("DIFF3D_NARROW", 0) || nx % k.V != 0 || !aligned)) k = kNarrow;
     const int zlen = env_int("DIFF3D_AZLEN", 0);
-    const bool wide = !env_int("DIFF3D_NARROW", 0) && nx % VW == 0 && (uintptr_t)lout % 16 == 0 &&
-                      (uintptr_t)lin % 16 == 0 && (uintptr_t)Ci % 16 == 0 && (uintptr_t)Tk % 16 == 0 &&
-                      (uintptr_t)gCi % 16 == 0;
-    if (wide) return launch_adj_cfg<DT, VW, 4, 4>(a, st, zlen);
-    return launch_adj_cfg<DT, 1, 4, 4>(a, st, zlen);
+    const int zdef = AdjDefaults<DT>::zdef;
+#define DIFF3D_TRY(v, r, nw) \
+    if (k.V == v && k.R == r && k.NW == nw) return launch_adj_cfg<DT, v, r, nw>(a, st, zlen, zdef);
+    if constexpr (sizeof(S) == 8) {
+        DIFF3D_ADJ_CFGS_8(DIFF3D_TRY)
+    } else {
+        DIFF3D_ADJ_CFGS_4(DIFF3D_TRY)
+    }
+#undef DIFF3D_TRY
+    return DIFF3D_EINVAL;
 }
 
 int adj_dispatch(int dtype, void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny,

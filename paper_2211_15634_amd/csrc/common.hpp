@@ -125,29 +125,39 @@ struct Traits<DIFF3D_BF16_RNE> {
 
 // ----------------------------------------------------------------- vectors
 // V consecutive elements of S moved as one naturally aligned load/store of
-// V*sizeof(S) bytes (2, 4, 8 or 16).
+// V*sizeof(S) bytes (2, 4, 8 or 16).  NT selects the non-temporal form
+// (streaming data that is not re-read by this launch).
+typedef unsigned int u32v2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32v4 __attribute__((ext_vector_type(4)));
 template <int BYTES>
 struct RawVec;
 template <> struct RawVec<2> { using T = uint16_t; };
 template <> struct RawVec<4> { using T = uint32_t; };
-template <> struct RawVec<8> { using T = uint2; };
-template <> struct RawVec<16> { using T = uint4; };
+template <> struct RawVec<8> { using T = u32v2; };
+template <> struct RawVec<16> { using T = u32v4; };
 
-template <class S, int V>
+template <class S, int V, bool NT = false>
 __device__ inline void vload(const S* p, S (&out)[V])
 {
     using R = typename RawVec<V * sizeof(S)>::T;
-    R r = *reinterpret_cast<const R*>(p);
+    R r;
+    if (NT)
+        r = __builtin_nontemporal_load(reinterpret_cast<const R*>(p));
+    else
+        r = *reinterpret_cast<const R*>(p);
     __builtin_memcpy(out, &r, sizeof(R));
 }
 
-template <class S, int V>
+template <class S, int V, bool NT = false>
 __device__ inline void vstore(S* p, const S (&in)[V])
 {
     using R = typename RawVec<V * sizeof(S)>::T;
     R r;
     __builtin_memcpy(&r, in, sizeof(R));
-    *reinterpret_cast<R*>(p) = r;
+    if (NT)
+        __builtin_nontemporal_store(r, reinterpret_cast<R*>(p));
+    else
+        *reinterpret_cast<R*>(p) = r;
 }
 
 // ----------------------------------------------------------------- mapping

@@ -6,6 +6,8 @@
 // -ffp-contract=off), so the FP64 form reproduces a plain loop bit for bit.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace diff3d {
@@ -72,8 +74,10 @@ __global__ __launch_bounds__(256) void step_naive(StepArgs<DT> a)
 //    barrier per plane); halo rows and columns of the tile are loaded by
 //    designated waves;
 //  - each element of T and Ci is read from HBM about once per step (halo
-//    re-reads of neighbouring tiles are L2 hits when they share an XCD).
-template <int DT, int V, int R, int NW>
+//    re-reads of neighbouring tiles are L2 hits when they share an XCD);
+//  - with NT, Ci is loaded and T2 stored non-temporally (neither is touched
+//    again by this launch).
+template <int DT, int V, int R, int NW, bool NT>
 __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, int nty, int zlen)
 {
     using Tr = Traits<DT>;
@@ -103,12 +107,12 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
     C hyl[V], hyh[V], hxl = C(0), hxr = C(0);        // halo of plane z+1
     C nyl[V], nyh[V], nxl = C(0), nxr = C(0);        // halo of plane z+2
 
-    auto load_rows = [&](const S* base, int z, C (&dst)[R][V]) {
+    auto load_rows = [&](const S* base, int z, C (&dst)[R][V], auto nt) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (xin && yw + r < ny) {
                 S raw[V];
-                vload<S, V>(base + (size_t)xl + sy * (yw + r) + sz * z, raw);
+                vload<S, V, decltype(nt)::value>(base + (size_t)xl + sy * (yw + r) + sz * z, raw);
 #pragma unroll
                 for (int v = 0; v < V; ++v) dst[r][v] = Tr::load(raw[v]);
             }
@@ -156,8 +160,10 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
         }
 #pragma unroll
     for (int v = 0; v < V; ++v) hyl[v] = hyh[v] = nyl[v] = nyh[v] = C(0);
-    load_rows(a.T, zb - 1, prev);
-    load_rows(a.T, zb, cur);
+    using Tmp = std::false_type;
+    using Str = std::integral_constant<bool, NT>;
+    load_rows(a.T, zb - 1, prev, Tmp{});
+    load_rows(a.T, zb, cur, Tmp{});
     {
         C yl[V], yh[V], xlo = C(0), xhi = C(0);
 #pragma unroll
@@ -165,17 +171,17 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
         load_halo(zb, yl, yh, xlo, xhi);
         stage(0, cur, yl, yh, xlo, xhi);
     }
-    load_rows(a.T, zb + 1, nxt);
+    load_rows(a.T, zb + 1, nxt, Tmp{});
     load_halo(zb + 1, hyl, hyh, hxl, hxr);
-    load_rows(a.Ci, zb, ci);
+    load_rows(a.Ci, zb, ci, Str{});
 
     int b = 0;
     for (int z = zb; z < ze; ++z) {
         const bool more = z + 1 < ze;
         if (more) {
-            load_rows(a.T, z + 2, nn);
+            load_rows(a.T, z + 2, nn, Tmp{});
             load_halo(z + 2, nyl, nyh, nxl, nxr);
-            load_rows(a.Ci, z + 1, ci2);
+            load_rows(a.Ci, z + 1, ci2, Str{});
         }
         lds_barrier();
         if (more) stage(b ^ 1, nxt, hyl, hyh, hxl, hxr);
@@ -209,7 +215,7 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
 #pragma unroll
             for (int v = 0; v < V; ++v) st[v] = Tr::store(out[v], rnd[v]);
             if (xl >= 1 && xl + V - 1 <= nx - 2) {
-                vstore<S, V>(a.T2 + i0, st);
+                vstore<S, V, NT>(a.T2 + i0, st);
             } else {
 #pragma unroll
                 for (int v = 0; v < V; ++v)

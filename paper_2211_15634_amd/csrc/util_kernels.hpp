@@ -44,19 +44,25 @@ __global__ __launch_bounds__(256) void fill_zero(uint4* __restrict__ p, size_t n
     if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
 }
 
-// Streaming copy, four 16-byte vectors in flight per thread per iteration.
-__global__ __launch_bounds__(256) void copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n16)
+// Streaming copy: each workgroup moves one contiguous chunk of 256*4
+// 16-byte vectors (all four loads in flight before the stores), with
+// non-temporal loads and stores.  One short-lived workgroup per 16 KiB keeps
+// the whole chip busy without a grid-stride loop.
+constexpr int kCopyUnroll = 4;
+__global__ __launch_bounds__(256) void copy16(u32v4* __restrict__ dst, const u32v4* __restrict__ src, size_t n16)
 {
-    const size_t stride = (size_t)gridDim.x * 256;
-    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
+    const size_t base = (size_t)blockIdx.x * (256 * kCopyUnroll) + threadIdx.x;
+    u32v4 v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const size_t i = base + (size_t)u * 256;
+        if (i < n16) v[u] = __builtin_nontemporal_load(src + i);
     }
-    for (; i < n16; i += stride) dst[i] = src[i];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const size_t i = base + (size_t)u * 256;
+        if (i < n16) __builtin_nontemporal_store(v[u], dst + i);
+    }
 }
 
 __global__ __launch_bounds__(256) void copy_u16(uint16_t* __restrict__ dst, const uint16_t* __restrict__ src,

@@ -82,3 +82,16 @@ def sample_points(shape, rng, k, include_edges=True):
     for _ in range(k):
         pts.append((int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))))
     return pts
+
+
+def instantiated_configs(kind: str, size: int):
+    """The tile configurations the library instantiates (read from its
+    source): kind "FWD" -> [(V, R, NW, NT)], kind "ADJ" -> [(V, R, NW)]."""
+    import os
+    import re
+    src = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2211_15634_amd",
+                       "csrc", "api.hip")
+    text = open(src).read().replace("\\\n", " ")
+    m = re.search(r"#define DIFF3D_%s_CFGS_%d\(X\)(.*)" % (kind, size), text)
+    assert m, (kind, size)
+    return [tuple(int(v) for v in t.split(",")) for t in re.findall(r"X\(([\d ,]+)\)", m.group(1))]

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads
-from helpers import norm_rel, oracle_reverse_at, sample_points, to_dev, to_host
+from helpers import instantiated_configs, norm_rel, oracle_reverse_at, sample_points, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -22,6 +22,7 @@ def _reset(lib):
     yield
     lib.set_kernel(lib.KERNEL_AUTO)
     os.environ.pop("DIFF3D_AZLEN", None)
+    os.environ.pop("DIFF3D_ACFG", None)
 
 
 def _inputs(shape, seed=0):
@@ -61,13 +62,30 @@ def test_fp64_matches_oracle_bitwise(lib, shape, nt, C, kernel):
         np.testing.assert_array_equal(gCi, rCi)
 
 
-@pytest.mark.parametrize("azlen", [1, 2, 5])
-def test_fp64_z_chunks(lib, azlen):
+def _adj_cases():
+    out = []
+    for name, size in (("f64", 8), ("f32", 4)):
+        for cfg in instantiated_configs("ADJ", size):
+            for azlen in (0, 1, 5):
+                out.append((name, cfg, azlen))
+    return out
+
+
+@pytest.mark.parametrize("dtype,cfg,azlen", _adj_cases())
+def test_adjoint_configs(lib, dtype, cfg, azlen):
+    """Every instantiated adjoint configuration and several z-chunk lengths:
+    FP64 bit-identical to the oracle, FP32 bit-identical to the naive kernel."""
     os.environ["DIFF3D_AZLEN"] = str(azlen)
+    os.environ["DIFF3D_ACFG"] = ",".join(str(c) for c in cfg)
     lib.set_kernel(lib.KERNEL_ZMARCH)
-    T0, Ci, g, s = _inputs((11, 23, 128), seed=azlen)
-    rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 5)
-    gT0, gCi = _adjoint(lib, T0, Ci, g, s, 5, 3)
+    T0, Ci, g, s = _inputs((11, 23, 128), seed=azlen + sum(cfg))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    gT0, gCi = _adjoint(lib, T0, Ci, g, s, 5, 3, dtype=tdt)
+    if dtype == "f64":
+        rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 5)
+    else:
+        lib.set_kernel(lib.KERNEL_NAIVE)
+        rT0, rCi = _adjoint(lib, T0, Ci, g, s, 5, 3, dtype=tdt)
     np.testing.assert_array_equal(gT0, rT0)
     np.testing.assert_array_equal(gCi, rCi)
 

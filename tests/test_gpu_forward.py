@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads
-from helpers import interior_mask, oracle_forward_at, sample_points, to_dev, to_host
+from helpers import instantiated_configs, interior_mask, oracle_forward_at, sample_points, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -67,18 +67,48 @@ def test_fp64_bit_exact(lib, shape, kernel):
         np.testing.assert_array_equal(to_host(T), ref)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
-@pytest.mark.parametrize("zlen", [0, 1, 3, 5])
-@pytest.mark.parametrize("narrow", [0, 1])
-def test_fp64_tilings_bit_exact(lib, cfg, zlen, narrow):
-    os.environ["DIFF3D_ZCFG"] = str(cfg)
-    os.environ["DIFF3D_ZLEN"] = str(zlen)
-    os.environ["DIFF3D_NARROW"] = str(narrow)
-    lib.set_kernel(lib.KERNEL_ZMARCH)
+def _cfg_cases():
+    out = []
+    for name, size in (("f64", 8), ("f32", 4), ("bf16", 2), ("bf16_rne", 2)):
+        for cfg in instantiated_configs("FWD", size):
+            for zlen in (0, 1, 3):
+                out.append((name, cfg, zlen))
+    return out
+
+
+@pytest.mark.parametrize("dtype,cfg,zlen", _cfg_cases())
+def test_zmarch_configs(lib, dtype, cfg, zlen):
+    """Every instantiated z-march configuration and several z-chunk lengths:
+    FP64 bit-identical to the oracle, other dtypes bit-identical to the
+    naive kernel (same operation order and random draws)."""
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "bf16_rne": torch.bfloat16}[dtype]
+    rounding = "rne" if dtype == "bf16_rne" else "sr"
     shape = (13, 45, 192)
-    T0, Ci, s = _inputs(shape, seed=cfg)
-    ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 4)
-    T, _ = _gpu_run(lib, T0, Ci, s, 4)
+    T0, Ci, s = _inputs(shape, seed=sum(cfg) + zlen)
+    os.environ["DIFF3D_ZLEN"] = str(zlen)
+    os.environ["DIFF3D_ZCFG"] = ",".join(str(c) for c in cfg)
+    lib.set_kernel(lib.KERNEL_ZMARCH)
+    lib.set_sr_seed(77, 0)
+    T, _ = _gpu_run(lib, T0, Ci, s, 4, dtype=tdt, rounding=rounding)
+    if dtype == "f64":
+        ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 4)
+        np.testing.assert_array_equal(to_host(T), ref)
+    else:
+        lib.set_kernel(lib.KERNEL_NAIVE)
+        lib.set_sr_seed(77, 0)
+        R, _ = _gpu_run(lib, T0, Ci, s, 4, dtype=tdt, rounding=rounding)
+        assert torch.equal(T, R)
+
+
+def test_narrow_fallback_ragged_rows(lib):
+    """A wide configuration on rows that are not a multiple of its vector
+    width falls back to one point per lane, still bit-exact."""
+    shape = (9, 21, 190)
+    T0, Ci, s = _inputs(shape)
+    os.environ["DIFF3D_ZCFG"] = "2,4,4,0"
+    lib.set_kernel(lib.KERNEL_ZMARCH)
+    ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 3)
+    T, _ = _gpu_run(lib, T0, Ci, s, 3)
     np.testing.assert_array_equal(to_host(T), ref)
 
 
