@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void adj_naive(AdjArgs<DT> a)
     const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (ix >= nx || iy >= ny) return;
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-    auto mu = [&](int x, int y, int z) -> C {
+    auto mu = [&](int x, int y, int z) __attribute__((always_inline)) -> C {
         if (x < 1 || x > nx - 2 || y < 1 || y > ny - 2 || z < 1 || z > nz - 2) return C(0);
         const size_t i = (size_t)x + sy * y + sz * z;
         return a.dtlam * Tr::load(a.Ci[i]) * Tr::load(a.lin[i]);
@@ -87,9 +87,9 @@ __global__ __launch_bounds__(64 * NW) void adj_zmarch(AdjArgs<DT> a, int ntx, in
     using S = typename Tr::S;
     using C = typename Tr::C;
     constexpr int TX = 64 * V, TY = R * NW, LW = TX + 2;
-    constexpr int WYL = 0, WYH = NW - 1;
-    constexpr int WXL = NW >= 3 ? 1 : 0, WXR = NW >= 4 ? 2 : NW - 1;
+    constexpr int WYL = 0, WYH = NW - 1, WXL = 1, WXR = 2;
     static_assert(TY <= 64, "x-halo columns are loaded by one lane per row");
+    static_assert(NW >= 4, "the four halo roles need four distinct waves");
     __shared__ C lmu[2][TY + 2][LW];
     __shared__ C lt[2][TY + 2][LW];
 
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(64 * NW) void adj_zmarch(AdjArgs<DT> a, int ntx, in
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
 
     // a point is interior if all three coordinates are
-    auto inner = [&](int x, int y, int z) {
+    auto inner = [&](int x, int y, int z) __attribute__((always_inline)) {
         return x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2 && z >= 1 && z <= nz - 2;
     };
     // mu and T at V consecutive points starting at (x, y, z); lambda too.
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(64 * NW) void adj_zmarch(AdjArgs<DT> a, int ntx, in
             m[v] = inner(x + v, y, z) ? a.dtlam * Tr::load(rc[v]) * lv[v] : C(0);
         }
     };
-    auto fetch1 = [&](int x, int y, int z, C& m, C& tv) {
+    auto fetch1 = [&](int x, int y, int z, C& m, C& tv) __attribute__((always_inline)) {
         m = tv = C(0);
         if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) return;
         const size_t i = (size_t)x + sy * y + sz * z;
@@ -136,12 +136,20 @@ __global__ __launch_bounds__(64 * NW) void adj_zmarch(AdjArgs<DT> a, int ntx, in
         m = inner(x, y, z) ? a.dtlam * Tr::load(a.Ci[i]) * Tr::load(a.lin[i]) : C(0);
     };
 
+    // Halo roles as in the forward z-march: one wave per role, so a thread
+    // holds at most one halo row (mu and T) and one halo column value.
+    const bool yrole = wave == WYL || wave == WYH;
+    const int yh = wave == WYL ? y0 - 1 : y0 + TY;
+    const int yrow = wave == WYL ? 0 : TY + 1;
+    const bool xrole = (wave == WXL || wave == WXR) && lane < TY;
+    const int xh = wave == WXL ? x0 - 1 : x0 + TX;
+    const int xcol = wave == WXL ? 0 : TX + 1;
+
     struct Plane {
         C m[R][V], tk[R][V], l[R][V];
-        C yl_m[V], yl_t[V], yh_m[V], yh_t[V];
-        C xl_m, xl_t, xr_m, xr_t;
+        C ym[V], yt[V], xm, xt;
     };
-    auto load_plane = [&](int z, Plane& p) {
+    auto load_plane = [&](int z, Plane& p) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (xin && yw + r < ny) {
@@ -152,15 +160,19 @@ __global__ __launch_bounds__(64 * NW) void adj_zmarch(AdjArgs<DT> a, int ntx, in
             }
         }
         C dummy[V];
+        if (yrole && xin) {
+            fetch(xl, yh, z, p.ym, p.yt, dummy);
+        } else {
 #pragma unroll
-        for (int v = 0; v < V; ++v) p.yl_m[v] = p.yl_t[v] = p.yh_m[v] = p.yh_t[v] = C(0);
-        p.xl_m = p.xl_t = p.xr_m = p.xr_t = C(0);
-        if (wave == WYL && xin) fetch(xl, y0 - 1, z, p.yl_m, p.yl_t, dummy);
-        if (wave == WYH && xin) fetch(xl, y0 + TY, z, p.yh_m, p.yh_t, dummy);
-        if (wave == WXL && lane < TY) fetch1(x0 - 1, y0 + lane, z, p.xl_m, p.xl_t);
-        if (wave == WXR && lane < TY) fetch1(x0 + TX, y0 + lane, z, p.xr_m, p.xr_t);
+            for (int v = 0; v < V; ++v) p.ym[v] = p.yt[v] = C(0);
+        }
+        if (xrole) {
+            fetch1(xh, y0 + lane, z, p.xm, p.xt);
+        } else {
+            p.xm = p.xt = C(0);
+        }
     };
-    auto stage = [&](int buf, const Plane& p) {
+    auto stage = [&](int buf, const Plane& p) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -168,40 +180,25 @@ __global__ __launch_bounds__(64 * NW) void adj_zmarch(AdjArgs<DT> a, int ntx, in
                 lmu[buf][1 + wave * R + r][1 + lane * V + v] = p.m[r][v];
                 lt[buf][1 + wave * R + r][1 + lane * V + v] = p.tk[r][v];
             }
-        if (wave == WYL)
+        if (yrole)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                lmu[buf][0][1 + lane * V + v] = p.yl_m[v];
-                lt[buf][0][1 + lane * V + v] = p.yl_t[v];
+                lmu[buf][yrow][1 + lane * V + v] = p.ym[v];
+                lt[buf][yrow][1 + lane * V + v] = p.yt[v];
             }
-        if (wave == WYH)
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                lmu[buf][TY + 1][1 + lane * V + v] = p.yh_m[v];
-                lt[buf][TY + 1][1 + lane * V + v] = p.yh_t[v];
-            }
-        if (wave == WXL && lane < TY) {
-            lmu[buf][1 + lane][0] = p.xl_m;
-            lt[buf][1 + lane][0] = p.xl_t;
-        }
-        if (wave == WXR && lane < TY) {
-            lmu[buf][1 + lane][TX + 1] = p.xr_m;
-            lt[buf][1 + lane][TX + 1] = p.xr_t;
+        if (xrole) {
+            lmu[buf][1 + lane][xcol] = p.xm;
+            lt[buf][1 + lane][xcol] = p.xt;
         }
     };
 
-    Plane P0, P1, P2, P3;   // planes z-1, z, z+1, z+2
-    load_plane(zb - 1, P0);
-    load_plane(zb, P1);
-    stage(0, P1);
-    load_plane(zb + 1, P2);
-
-    int b = 0;
-    for (int z = zb; z < ze; ++z) {
+    // One output plane z from planes z-1 (p0), z (p1, staged in LDS buffer
+    // buf) and z+1 (p2); plane z+2 is prefetched into p3 and p2 is staged.
+    auto body = [&](int z, int buf, const Plane& p0, const Plane& p1, const Plane& p2, Plane& p3) __attribute__((always_inline)) {
         const bool more = z + 1 < ze;
-        if (more) load_plane(z + 2, P3);
+        if (more) load_plane(z + 2, p3);
         lds_barrier();
-        if (more) stage(b ^ 1, P2);
+        if (more) stage(buf ^ 1, p2);
 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -216,19 +213,19 @@ __global__ __launch_bounds__(64 * NW) void adj_zmarch(AdjArgs<DT> a, int ntx, in
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int col = 1 + lane * V + v;
-                const C mxm = v > 0 ? P1.m[r][v - 1] : lmu[b][row][col - 1];
-                const C mxp = v < V - 1 ? P1.m[r][v + 1] : lmu[b][row][col + 1];
-                const C mym = r > 0 ? P1.m[r - 1][v] : lmu[b][row - 1][col];
-                const C myp = r < R - 1 ? P1.m[r + 1][v] : lmu[b][row + 1][col];
-                const C lm = lap7<DT>(P1.m[r][v], mxm, mxp, mym, myp, P0.m[r][v], P2.m[r][v], a);
-                lo[v] = Tr::store(P1.l[r][v] + lm, 0);
+                const C mxm = v > 0 ? p1.m[r][v - 1] : lmu[buf][row][col - 1];
+                const C mxp = v < V - 1 ? p1.m[r][v + 1] : lmu[buf][row][col + 1];
+                const C mym = r > 0 ? p1.m[r - 1][v] : lmu[buf][row - 1][col];
+                const C myp = r < R - 1 ? p1.m[r + 1][v] : lmu[buf][row + 1][col];
+                const C lm = lap7<DT>(p1.m[r][v], mxm, mxp, mym, myp, p0.m[r][v], p2.m[r][v], a);
+                lo[v] = Tr::store(p1.l[r][v] + lm, 0);
                 if (rowin) {
-                    const C txm = v > 0 ? P1.tk[r][v - 1] : lt[b][row][col - 1];
-                    const C txp = v < V - 1 ? P1.tk[r][v + 1] : lt[b][row][col + 1];
-                    const C tym = r > 0 ? P1.tk[r - 1][v] : lt[b][row - 1][col];
-                    const C typ = r < R - 1 ? P1.tk[r + 1][v] : lt[b][row + 1][col];
-                    const C ltk = lap7<DT>(P1.tk[r][v], txm, txp, tym, typ, P0.tk[r][v], P2.tk[r][v], a);
-                    go[v] = Tr::store(Tr::load(gr[v]) + a.dtlam * P1.l[r][v] * ltk, 0);
+                    const C txm = v > 0 ? p1.tk[r][v - 1] : lt[buf][row][col - 1];
+                    const C txp = v < V - 1 ? p1.tk[r][v + 1] : lt[buf][row][col + 1];
+                    const C tym = r > 0 ? p1.tk[r - 1][v] : lt[buf][row - 1][col];
+                    const C typ = r < R - 1 ? p1.tk[r + 1][v] : lt[buf][row + 1][col];
+                    const C ltk = lap7<DT>(p1.tk[r][v], txm, txp, tym, typ, p0.tk[r][v], p2.tk[r][v], a);
+                    go[v] = Tr::store(Tr::load(gr[v]) + a.dtlam * p1.l[r][v] * ltk, 0);
                 }
             }
             vstore<S, V>(a.lout + i0, lo);
@@ -242,11 +239,23 @@ __global__ __launch_bounds__(64 * NW) void adj_zmarch(AdjArgs<DT> a, int ntx, in
                 }
             }
         }
+    };
 
+    // plane z sits in LDS buffer (z - zb) & 1; the plane sets shift down by
+    // one after each plane
+    Plane P0, P1, P2, P3;
+    load_plane(zb - 1, P0);
+    load_plane(zb, P1);
+    stage(0, P1);
+    load_plane(zb + 1, P2);
+    load_plane(-1, P3);   // zero-filled: plane -1 is outside the grid
+    int buf = 0;
+    for (int z = zb; z < ze; ++z) {
+        body(z, buf, P0, P1, P2, P3);
         P0 = P1;
         P1 = P2;
         P2 = P3;
-        b ^= 1;
+        buf ^= 1;
     }
 }
 

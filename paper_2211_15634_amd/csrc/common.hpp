@@ -37,9 +37,9 @@ __host__ __device__ inline u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// Random 16-bit word for point `idx` at step `step`: one Philox call covers
-// the 8 consecutive points idx & ~7 (two 16-bit halves of four 32-bit words),
-// so every kernel variant draws the same bits for the same point.
+// Random bits for point `idx` at step `step`: one Philox call covers the 8
+// consecutive points idx & ~7 (the two 16-bit halves of its four 32-bit
+// words), so every kernel variant draws the same bits for the same point.
 struct SrState {
     uint32_t k0, k1;     // seed
     uint32_t s0, s1;     // step index
@@ -50,36 +50,36 @@ __device__ inline u32x4 sr_block(const SrState& st, size_t group)
     return philox4x32_10(u32x4{(uint32_t)group, (uint32_t)(group >> 32), st.s0, st.s1}, st.k0, st.k1);
 }
 
-__device__ inline uint32_t sr_pick(const u32x4& r, unsigned j)   // j = idx & 7
+// The 16 random bits of point j = idx & 7, placed in the upper half of the
+// word (the half the rounding instruction reads).
+__device__ inline uint32_t sr_word(const u32x4& r, unsigned j)
 {
     const uint32_t w = (j >> 1) == 0 ? r.x : (j >> 1) == 1 ? r.y : (j >> 1) == 2 ? r.z : r.w;
-    return (j & 1) ? (w >> 16) : (w & 0xFFFFu);
+    return (j & 1) ? (w & 0xFFFF0000u) : (w << 16);
 }
 
 // ----------------------------------------------------------------- BF16
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 __device__ inline float bf16_to_f32(uint16_t h)
 {
     return __uint_as_float((uint32_t)h << 16);
 }
 
+// Round to nearest even (v_cvt_pk_bf16_f32 on gfx950; NaN stays NaN).
 __device__ inline uint16_t f32_to_bf16_rne(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x0040u);  // quiet NaN
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
-// Stochastic rounding: add 16 random bits below the kept mantissa and
-// truncate, so the value rounds up with probability equal to the discarded
-// fraction of an ulp (unbiased in expectation).
-__device__ inline uint16_t f32_to_bf16_sr(float f, uint32_t rnd16)
+// Stochastic rounding (v_cvt_sr_bf16_f32): the instruction adds the upper 16
+// bits of `rnd` below the kept mantissa and truncates, so a value rounds up
+// with probability equal to the discarded fraction of an ulp (unbiased in
+// expectation); NaN and infinities are kept.
+__device__ inline uint16_t f32_to_bf16_sr(float f, uint32_t rnd)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x0040u);
-    if ((u & 0x7FFFFFFFu) == 0x7F800000u) return (uint16_t)(u >> 16);            // +-inf
-    u += rnd16;
-    return (uint16_t)(u >> 16);
+    const bf16x2_t v = __builtin_amdgcn_cvt_sr_bf16_f32(bf16x2_t{}, f, rnd, false);
+    return (uint16_t)(__builtin_bit_cast(uint32_t, v) & 0xFFFFu);
 }
 
 // ----------------------------------------------------------------- dtypes

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void step_naive(StepArgs<DT> a)
                                       Tr::load(a.T[i + sy]), Tr::load(a.T[i - sz]), Tr::load(a.T[i + sz]),
                                       Tr::load(a.Ci[i]), a);
         uint32_t rnd = 0;
-        if (Tr::sr) rnd = sr_pick(sr_block(a.sr, i >> 3), (unsigned)(i & 7));
+        if constexpr (Tr::sr) rnd = sr_word(sr_block(a.sr, i >> 3), (unsigned)(i & 7));
         a.T2[i] = Tr::store(r, rnd);
     }
 }
@@ -65,8 +65,8 @@ __global__ __launch_bounds__(256) void step_naive(StepArgs<DT> a)
 // ------------------------------------------------------------------ z-march
 // A workgroup of NW wave64s owns an x-y tile of TX = 64*V by TY = R*NW
 // points and marches along z over `zlen` output planes.  Lane l of wave w
-// holds V consecutive x points (one 16-byte load when V > 1) of the R
-// consecutive rows y0 + w*R .. y0 + w*R + R-1.
+// holds V consecutive x points (one load of V*sizeof(S) <= 16 bytes) of the
+// R consecutive rows y0 + w*R .. y0 + w*R + R-1.
 //  - z neighbours: three planes (z-1, z, z+1) of the thread's points live in
 //    registers, and the plane z+2 is loaded one iteration ahead;
 //  - x and y neighbours inside the thread come from registers, the others
@@ -84,9 +84,9 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
     using S = typename Tr::S;
     using C = typename Tr::C;
     constexpr int TX = 64 * V, TY = R * NW, LW = TX + 2;
-    constexpr int WYL = 0, WYH = NW - 1;
-    constexpr int WXL = NW >= 3 ? 1 : 0, WXR = NW >= 4 ? 2 : NW - 1;
+    constexpr int WYL = 0, WYH = NW - 1, WXL = 1, WXR = 2;
     static_assert(TY <= 64, "x-halo columns are loaded by one lane per row");
+    static_assert(NW >= 4, "the four halo roles need four distinct waves");
     __shared__ C lds[2][TY + 2][LW];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -103,11 +103,24 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
     const int yw = y0 + wave * R;        // first row of this thread
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
 
-    C prev[R][V], cur[R][V], nxt[R][V], nn[R][V], ci[R][V], ci2[R][V];
-    C hyl[V], hyh[V], hxl = C(0), hxr = C(0);        // halo of plane z+1
-    C nyl[V], nyh[V], nxl = C(0), nxr = C(0);        // halo of plane z+2
+    // Each halo role belongs to one wave (NW >= 4): wave WYL loads the row
+    // below the tile, WYH the row above, WXL and WXR the columns left and
+    // right of it; so a thread holds at most one halo row vector and one
+    // halo column value.
+    struct Halo {
+        C y[V], x;
+    };
+    using Rows = C[R][V];
+    const bool yrole = wave == WYL || wave == WYH;
+    const int yh = wave == WYL ? y0 - 1 : y0 + TY;             // halo row of a y-role wave
+    const int yrow = wave == WYL ? 0 : TY + 1;                 // its LDS row
+    const bool xrole = (wave == WXL || wave == WXR) && lane < TY;
+    const int xh = wave == WXL ? x0 - 1 : x0 + TX;              // halo column of an x-role wave
+    const int xcol = wave == WXL ? 0 : TX + 1;                  // its LDS column
+    const bool yload = yrole && xin && yh >= 0 && yh < ny;
+    const bool xload = xrole && y0 + lane < ny && xh >= 0 && xh < nx;
 
-    auto load_rows = [&](const S* base, int z, C (&dst)[R][V], auto nt) {
+    auto load_rows = [&](const S* base, int z, Rows& dst, auto nt) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (xin && yw + r < ny) {
@@ -118,74 +131,26 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
             }
         }
     };
-    auto load_halo = [&](int z, C (&yl)[V], C (&yh)[V], C& xlo, C& xhi) {
-        if (wave == WYL && xin && y0 >= 1) {
+    auto load_halo = [&](int z, Halo& h) __attribute__((always_inline)) {
+        if (yload) {
             S raw[V];
-            vload<S, V>(a.T + (size_t)xl + sy * (y0 - 1) + sz * z, raw);
+            vload<S, V>(a.T + (size_t)xl + sy * yh + sz * z, raw);
 #pragma unroll
-            for (int v = 0; v < V; ++v) yl[v] = Tr::load(raw[v]);
+            for (int v = 0; v < V; ++v) h.y[v] = Tr::load(raw[v]);
         }
-        if (wave == WYH && xin && y0 + TY < ny) {
-            S raw[V];
-            vload<S, V>(a.T + (size_t)xl + sy * (y0 + TY) + sz * z, raw);
-#pragma unroll
-            for (int v = 0; v < V; ++v) yh[v] = Tr::load(raw[v]);
-        }
-        if (wave == WXL && lane < TY && y0 + lane < ny && x0 >= 1)
-            xlo = Tr::load(a.T[(size_t)(x0 - 1) + sy * (y0 + lane) + sz * z]);
-        if (wave == WXR && lane < TY && y0 + lane < ny && x0 + TX < nx)
-            xhi = Tr::load(a.T[(size_t)(x0 + TX) + sy * (y0 + lane) + sz * z]);
+        if (xload) h.x = Tr::load(a.T[(size_t)xh + sy * (y0 + lane) + sz * z]);
     };
-    auto stage = [&](int buf, const C (&c)[R][V], const C (&yl)[V], const C (&yh)[V], C xlo, C xhi) {
+    auto stage = [&](int buf, const Rows& c, const Halo& h) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int v = 0; v < V; ++v) lds[buf][1 + wave * R + r][1 + lane * V + v] = c[r][v];
-        if (wave == WYL)
+        if (yrole)
 #pragma unroll
-            for (int v = 0; v < V; ++v) lds[buf][0][1 + lane * V + v] = yl[v];
-        if (wave == WYH)
-#pragma unroll
-            for (int v = 0; v < V; ++v) lds[buf][TY + 1][1 + lane * V + v] = yh[v];
-        if (wave == WXL && lane < TY) lds[buf][1 + lane][0] = xlo;
-        if (wave == WXR && lane < TY) lds[buf][1 + lane][TX + 1] = xhi;
+            for (int v = 0; v < V; ++v) lds[buf][yrow][1 + lane * V + v] = h.y[v];
+        if (xrole) lds[buf][1 + lane][xcol] = h.x;
     };
-
-    // prologue: planes zb-1, zb (staged), zb+1 (+ halo) and Ci at zb
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            prev[r][v] = cur[r][v] = nxt[r][v] = nn[r][v] = ci[r][v] = ci2[r][v] = C(0);
-        }
-#pragma unroll
-    for (int v = 0; v < V; ++v) hyl[v] = hyh[v] = nyl[v] = nyh[v] = C(0);
-    using Tmp = std::false_type;
-    using Str = std::integral_constant<bool, NT>;
-    load_rows(a.T, zb - 1, prev, Tmp{});
-    load_rows(a.T, zb, cur, Tmp{});
-    {
-        C yl[V], yh[V], xlo = C(0), xhi = C(0);
-#pragma unroll
-        for (int v = 0; v < V; ++v) yl[v] = yh[v] = C(0);
-        load_halo(zb, yl, yh, xlo, xhi);
-        stage(0, cur, yl, yh, xlo, xhi);
-    }
-    load_rows(a.T, zb + 1, nxt, Tmp{});
-    load_halo(zb + 1, hyl, hyh, hxl, hxr);
-    load_rows(a.Ci, zb, ci, Str{});
-
-    int b = 0;
-    for (int z = zb; z < ze; ++z) {
-        const bool more = z + 1 < ze;
-        if (more) {
-            load_rows(a.T, z + 2, nn, Tmp{});
-            load_halo(z + 2, nyl, nyh, nxl, nxr);
-            load_rows(a.Ci, z + 1, ci2, Str{});
-        }
-        lds_barrier();
-        if (more) stage(b ^ 1, nxt, hyl, hyh, hxl, hxr);
-
+    auto compute = [&](int z, int buf, const Rows& prev, const Rows& cur, const Rows& nxt, const Rows& ci) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = yw + r;
@@ -195,25 +160,22 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int col = 1 + lane * V + v;
-                const C xm = v > 0 ? cur[r][v - 1] : lds[b][row][col - 1];
-                const C xp = v < V - 1 ? cur[r][v + 1] : lds[b][row][col + 1];
-                const C ym = r > 0 ? cur[r - 1][v] : lds[b][row - 1][col];
-                const C yp = r < R - 1 ? cur[r + 1][v] : lds[b][row + 1][col];
+                const C xm = v > 0 ? cur[r][v - 1] : lds[buf][row][col - 1];
+                const C xp = v < V - 1 ? cur[r][v + 1] : lds[buf][row][col + 1];
+                const C ym = r > 0 ? cur[r - 1][v] : lds[buf][row - 1][col];
+                const C yp = r < R - 1 ? cur[r + 1][v] : lds[buf][row + 1][col];
                 out[v] = stencil_point<DT>(cur[r][v], xm, xp, ym, yp, prev[r][v], nxt[r][v], ci[r][v], a);
             }
             const size_t i0 = (size_t)xl + sy * y + sz * z;
-            uint32_t rnd[V];
-            if (Tr::sr) {
+            S st[V];
+            if constexpr (Tr::sr) {
                 const u32x4 rb = sr_block(a.sr, i0 >> 3);
 #pragma unroll
-                for (int v = 0; v < V; ++v) rnd[v] = sr_pick(rb, (unsigned)((i0 + v) & 7));
+                for (int v = 0; v < V; ++v) st[v] = Tr::store(out[v], sr_word(rb, (unsigned)((i0 + v) & 7)));
             } else {
 #pragma unroll
-                for (int v = 0; v < V; ++v) rnd[v] = 0;
+                for (int v = 0; v < V; ++v) st[v] = Tr::store(out[v], 0);
             }
-            S st[V];
-#pragma unroll
-            for (int v = 0; v < V; ++v) st[v] = Tr::store(out[v], rnd[v]);
             if (xl >= 1 && xl + V - 1 <= nx - 2) {
                 vstore<S, V, NT>(a.T2 + i0, st);
             } else {
@@ -222,24 +184,68 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
                     if (xl + v >= 1 && xl + v <= nx - 2) a.T2[i0 + v] = st[v];
             }
         }
+    };
+    using Tmp = std::false_type;
+    using Str = std::integral_constant<bool, NT>;
+    // One plane z: prefetch plane z+2 (into nn, hn) and Ci of z+1 (into ci2),
+    // barrier, stage plane z+1 (nxt, hc) into the other LDS buffer, compute z.
+    auto body = [&](int z, int buf, const Rows& prev, const Rows& cur, const Rows& nxt, Rows& nn, const Rows& ci,
+                    Rows& ci2, const Halo& hc, Halo& hn) __attribute__((always_inline)) {
+        const bool more = z + 1 < ze;
+        if (more) {
+            load_rows(a.T, z + 2, nn, Tmp{});
+            load_halo(z + 2, hn);
+            load_rows(a.Ci, z + 1, ci2, Str{});
+        }
+        lds_barrier();
+        if (more) stage(buf ^ 1, nxt, hc);
+        compute(z, buf, prev, cur, nxt, ci);
+    };
 
+    Rows pa, pb, pc, pd, ca, cb;
+    Halo ha, hb;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int v = 0; v < V; ++v) pa[r][v] = pb[r][v] = pc[r][v] = pd[r][v] = ca[r][v] = cb[r][v] = C(0);
+#pragma unroll
+    for (int v = 0; v < V; ++v) ha.y[v] = hb.y[v] = C(0);
+    ha.x = hb.x = C(0);
+
+    // prologue: planes zb-1, zb (staged in LDS buffer 0), zb+1 with its halo, Ci at zb
+    load_rows(a.T, zb - 1, pa, Tmp{});
+    load_rows(a.T, zb, pb, Tmp{});
+    {
+        Halo h0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) h0.y[v] = C(0);
+        h0.x = C(0);
+        load_halo(zb, h0);
+        stage(0, pb, h0);
+    }
+    load_rows(a.T, zb + 1, pc, Tmp{});
+    load_halo(zb + 1, ha);
+    load_rows(a.Ci, zb, ca, Str{});
+
+    // plane z sits in LDS buffer (z - zb) & 1; after each plane the buffers
+    // shift down by one (a single loop body keeps the kernel small enough
+    // for the instruction cache)
+    int buf = 0;
+    for (int z = zb; z < ze; ++z) {
+        body(z, buf, pa, pb, pc, pd, ca, cb, ha, hb);
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                prev[r][v] = cur[r][v];
-                cur[r][v] = nxt[r][v];
-                nxt[r][v] = nn[r][v];
-                ci[r][v] = ci2[r][v];
+                pa[r][v] = pb[r][v];
+                pb[r][v] = pc[r][v];
+                pc[r][v] = pd[r][v];
+                ca[r][v] = cb[r][v];
             }
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            hyl[v] = nyl[v];
-            hyh[v] = nyh[v];
-        }
-        hxl = nxl;
-        hxr = nxr;
-        b ^= 1;
+        for (int v = 0; v < V; ++v) ha.y[v] = hb.y[v];
+        ha.x = hb.x;
+        buf ^= 1;
     }
 }
 
