@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only: no precision, adjoint or CPU legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only launch a 1 GiB copy and the step kernel, 3 times each (for counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -88,6 +90,26 @@ def main():
     torch.cuda.set_device(dev)
     n, nt = args.n, args.nt
     N = n * n * n
+
+    if args.traffic_probe:
+        # A copy of known size calibrates the FETCH_SIZE / WRITE_SIZE counters;
+        # then the forward step kernel on the benchmark workload.
+        src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            d3.copy_(dst, src)
+        torch.cuda.synchronize()
+        del src, dst
+        T0h, Cih = workloads.bump(n, n, n)
+        T = torch.from_numpy(T0h).to(dev)
+        Ci = torch.from_numpy(Cih).to(dev)
+        s = d3.problem_scalars(Ci)
+        T2 = T.clone()
+        for _ in range(3):
+            d3.step(T2, T, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+        torch.cuda.synchronize()
+        log("traffic probe done: 3 copies of 1 GiB, 3 steps of bump%d FP64" % n)
+        return
     log("bench: generating bump%d inputs" % n)
     T0h, Cih = workloads.bump(n, n, n)
     T0 = torch.from_numpy(T0h).to(dev)
