@@ -61,6 +61,50 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def large_form(d3, workloads, torch, np, dev, stream, n=1024, nt=500, C=32):
+    """1024^3 FP32: T0 ~ U[0,1] (seed 0), Ci = 0.5, T_target ~ U[0,1] (seed 2);
+    forward with a checkpoint every C steps, FP64 loss on the GPU, reverse
+    sweep.  Returns timings and T_eff of the forward and reverse sweeps."""
+    N = n ** 3
+    esz = 4
+    T0 = torch.from_numpy(workloads.uniform(n, n, n, workloads.SEED_T0).astype(np.float32)).to(dev)
+    Ci = torch.full((n, n, n), 0.5, dtype=torch.float32, device=dev)
+    s = d3.problem_scalars(Ci)
+    sc = (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+    ws_bytes = d3.adjoint_workspace_bytes(T0.shape, nt, C, torch.float32)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    T = T0.clone()
+    T2 = torch.empty_like(T0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    d3.run(T, T2, Ci, *sc, nt, ckpt=ws, ckpt_every=C)
+    ev[1].record(stream)
+    Tt = torch.from_numpy(workloads.target(n, n, n).astype(np.float32)).to(dev)
+    loss = d3.loss(T, Tt, T2)          # T2 now holds the seed dL/dT_nt
+    del Tt
+    gT0 = torch.empty_like(T0)
+    gCi = torch.empty_like(T0)
+    ev[2].record(stream)
+    d3.adjoint_run(T0, Ci, T2, gT0, gCi, ws, True, *sc, nt, C)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    tf = ev[0].elapsed_time(ev[1]) / 1e3
+    tb = ev[2].elapsed_time(ev[3]) / 1e3
+    nck = (nt + C - 1) // C
+    recompute = nt - nck
+    gnorm = float(d3.norm2(gT0)) ** 0.5
+    finite = bool(torch.isfinite(gT0).all() and torch.isfinite(gCi).all())
+    out = {"large_workload": "1024^3 FP32, nt=%d, checkpoint every %d (%d checkpoints), workspace %.1f GB"
+                             % (nt, C, nck, ws_bytes / 1e9),
+           "large_fwd_s": round(tf, 4), "large_bwd_s": round(tb, 4), "large_ratio": round(tb / tf, 3),
+           "large_teff_fwd_GBps": round(3 * esz * N * nt / tf / 1e9, 1),
+           "large_teff_bwd_GBps": round((3 * recompute + 6 * nt) * esz * N / tb / 1e9, 1),
+           "large_loss": float(loss), "large_gradnorm_T0": gnorm, "large_finite": finite}
+    del T0, Ci, ws, T, T2, gT0, gCi
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +115,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only: no precision, adjoint or CPU legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--large", action="store_true",
+                    help="also run the 1024^3 FP32 forward + checkpointed adjoint form (nt=500, C=32, ~240 GB)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch a 1 GiB copy and the step kernel, 3 times each (for counter runs)")
     args = ap.parse_args()
@@ -251,6 +297,13 @@ def main():
             del X0, Cg, Tt, ws, Tg, T2g, seed, gT0, gCi
             torch.cuda.empty_cache()
         log("bench: adjoint", {k: v for k, v in extra.items() if k.startswith("adjoint")})
+
+    # ---------------------------------------------------------- large adjoint form
+    if args.large:
+        del T
+        torch.cuda.empty_cache()
+        extra.update(large_form(d3, workloads, torch, np, dev, stream))
+        log("bench: large form", {k: v for k, v in extra.items() if k.startswith("large")})
 
     # ---------------------------------------------------------- CPU baseline
     cpu = None
