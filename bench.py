@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "traffic_step_zmarch_bump512_f64.json")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_step_tb2_bump512_f64.json")
 METRIC = "T_eff GB/s (% HBM peak) per 3-D diffusion step; adjoint/forward time ratio"
 
 
@@ -118,7 +118,8 @@ def main():
     ap.add_argument("--large", action="store_true",
                     help="also run the 1024^3 FP32 forward + checkpointed adjoint form (nt=500, C=32, ~240 GB)")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="only launch a 1 GiB copy and the step kernel, 3 times each (for counter runs)")
+                    help="only launch a 1 GiB copy, the two-step and the single-step kernel, 3 times each "
+                         "(for counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -152,9 +153,11 @@ def main():
         s = d3.problem_scalars(Ci)
         T2 = T.clone()
         for _ in range(3):
+            d3.step2(T2, T, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+        for _ in range(3):
             d3.step(T2, T, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
         torch.cuda.synchronize()
-        log("traffic probe done: 3 copies of 1 GiB, 3 steps of bump%d FP64" % n)
+        log("traffic probe done: 3 copies of 1 GiB, 3 two-step and 3 single-step launches on bump%d FP64" % n)
         return
     log("bench: generating bump%d inputs" % n)
     T0h, Cih = workloads.bump(n, n, n)
@@ -191,20 +194,28 @@ def main():
         raise RuntimeError("non-finite values after the timed runs")
     log("bench: %.3f ms per run of %d steps, T_eff %.1f GB/s (wall %.3f s)" % (ms_per_step, nt, teff, wall))
 
-    # ---------------------------------------------------------- kernel duration
-    # one diff3d_step launch between two events, on the stream it runs on
-    M = 40
-    kev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * M)]
-    a, b = T, T2
-    for i in range(M):
-        kev[2 * i].record(stream)
-        d3.step(b, a, Ci, *sc)
-        kev[2 * i + 1].record(stream)
-        a, b = b, a
-    torch.cuda.synchronize()
-    kms = [kev[2 * i].elapsed_time(kev[2 * i + 1]) for i in range(M)]
-    k_avg_ms = sum(kms) / M
-    achieved = bytes_step / (k_avg_ms / 1e3) / 1e9
+    # ---------------------------------------------------------- kernel durations
+    # one launch between two events, on the stream it runs on: the two-step
+    # kernel (what the time loop runs for FP64) and the single-step kernel
+    def kernel_ms(fn, reps=100, warm=30):
+        # the clocks settle over the first tens of launches after an idle gap:
+        # launch `warm` unrecorded ones first
+        kev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        a, b = T, T2
+        for i in range(warm):
+            fn(b, a)
+            a, b = b, a
+        for i in range(reps):
+            kev[2 * i].record(stream)
+            fn(b, a)
+            kev[2 * i + 1].record(stream)
+            a, b = b, a
+        torch.cuda.synchronize()
+        return sum(kev[2 * i].elapsed_time(kev[2 * i + 1]) for i in range(reps)) / reps
+
+    k2_ms = kernel_ms(lambda b, a: d3.step2(b, a, Ci, *sc))
+    k1_ms = kernel_ms(lambda b, a: d3.step(b, a, Ci, *sc))
+    achieved = 2 * bytes_step / (k2_ms / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -213,9 +224,13 @@ def main():
             traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "step_zmarch", "kernel_avg_us": round(k_avg_ms * 1e3, 2),
-                "algorithmic_bytes_per_launch": bytes_step}
-    log("bench: step kernel %.1f us, %.1f GB/s" % (k_avg_ms * 1e3, achieved))
+                "kernel": "step_tb2 (two steps per launch)", "kernel_avg_us": round(k2_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": 2 * bytes_step,
+                "hbm_GBps": round(traffic / (k2_ms / 1e3) / 1e9, 1) if traffic else None}
+    single = {"kernel": "step_zmarch (one step per launch)", "kernel_avg_us": round(k1_ms * 1e3, 2),
+              "teff_GBps": round(bytes_step / (k1_ms / 1e3) / 1e9, 1)}
+    log("bench: two-step kernel %.1f us (%.1f GB/s algorithmic), single-step kernel %.1f us (%.1f GB/s)"
+        % (k2_ms * 1e3, achieved, k1_ms * 1e3, single["teff_GBps"]))
 
     # ---------------------------------------------------------- copy bandwidth
     del T2
@@ -290,9 +305,20 @@ def main():
                 torch.cuda.synchronize()
             tf = ev[0].elapsed_time(ev[1])
             tb = ev[2].elapsed_time(ev[3])
+            # the same forward with single-step launches (the paper's step)
+            d3.set_kernel(d3.KERNEL_ZMARCH)
+            Tg.copy_(X0)
+            ev[0].record(stream)
+            d3.run(Tg, T2g, Cg, *scg, ntg, ckpt=ws, ckpt_every=C)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            d3.set_kernel(d3.KERNEL_AUTO)
+            tf1 = ev[0].elapsed_time(ev[1])
             extra["adjoint_%s_256_fwd_ms" % tag] = round(tf, 3)
+            extra["adjoint_%s_256_fwd_single_step_ms" % tag] = round(tf1, 3)
             extra["adjoint_%s_256_bwd_ms" % tag] = round(tb, 3)
             extra["adjoint_%s_256_ratio" % tag] = round(tb / tf, 3)
+            extra["adjoint_%s_256_ratio_vs_single_step" % tag] = round(tb / tf1, 3)
             extra["adjoint_%s_256_gradnorm" % tag] = float(d3.norm2(gT0)) ** 0.5
             del X0, Cg, Tt, ws, Tg, T2g, seed, gT0, gCi
             torch.cuda.empty_cache()
@@ -341,7 +367,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "bump%d FP64: 3-D heat diffusion %d^3, nt=%d per step, Gaussian bump + 0.01 U[0,1] "
                                "noise, Ci=0.5(1+0.5u), lam=1, dt=min(dx^2)/lam/max(Ci)/6.1" % (n, n, nt),
-                   "nx": n, "ny": n, "nz": n, "nt": nt, "kernel": "zmarch", "parallelism": "single GPU"},
+                   "nx": n, "ny": n, "nz": n, "nt": nt, "kernel": "two-step z-march (temporal blocking)",
+                   "parallelism": "single GPU"},
         "t_step_us": round(t_step * 1e6, 3),
         "teff_frac_hbm_peak": round(teff / HBM_PEAK_GBPS, 4),
         "copy_GBps": round(copy_gbps, 1),
@@ -349,6 +376,7 @@ def main():
         "run_ms_median": round(med, 4),
         "run_ms_ci95": [round(lo, 4), round(hi, 4)],
         "roofline": roofline,
+        "single_step": single,
         "cpu_baseline": cpu,
     }
     out.update(extra)

@@ -58,9 +58,12 @@ typedef enum {
 } diff3d_status;
 
 typedef enum {
-    DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant for the shape */
+    DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps, and in
+                                  diff3d_run two-step passes for FP64 and FP32 */
     DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */
-    DIFF3D_KERNEL_ZMARCH = 2   /* x-y tiles marching along z, planes in registers and LDS */
+    DIFF3D_KERNEL_ZMARCH = 2,  /* x-y tiles marching along z, planes in registers and LDS */
+    DIFF3D_KERNEL_TB2 = 3      /* diff3d_run: two steps per pass (temporal blocking), z-march
+                                  for single steps; bit-identical results */
 } diff3d_kernel;
 
 /* Number of doubles in the device buffer `acc` of the reductions below. */
@@ -93,6 +96,15 @@ int diff3d_max(const void* x, size_t n, int dtype, double* acc, void* stream);
  * (seed, step_index, point), see diff3d_set_sr_seed. */
 int diff3d_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
                 double dt, double rdx, double rdy, double rdz, int dtype, void* stream);
+
+/* Two time steps in one pass over memory (temporal blocking): writes the
+ * interior of T2 with the state two steps after T, bit-identical to two
+ * diff3d_step calls through an intermediate buffer (the intermediate is
+ * rounded exactly as storing it would round it; stochastic rounding uses
+ * step indices s and s+1 and advances the index by 2).  Same buffer rules
+ * as diff3d_step: T2's boundary is not touched, T2 must not alias T or Ci. */
+int diff3d_step2(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
+                 double dt, double rdx, double rdy, double rdz, int dtype, void* stream);
 
 /* nt time steps with the buffer swap of Fig. 1.  First copies T's boundary
  * into T2, then alternates steps T -> T2 -> T ...  The result T_nt is always

@@ -1,7 +1,7 @@
 """Python binding of libdiff3d, the MI355X (gfx950) 3-D heat-diffusion library.
 
 Argument marshalling only: every step runs in the HIP kernels of
-``libdiff3d.so`` (built by ``paper_2211_15634_amd.build``).  PyTorch supplies
+``libdiff3d.so`` (built by ``paper_2211_15634_amd/build.py``).  PyTorch supplies
 device memory and the current stream.  If the library is missing this module
 raises ImportError: there is no fallback path.
 
@@ -24,14 +24,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdiff3d.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libdiff3d.so is not built; run `python -m paper_2211_15634_amd.build` "
+    raise ImportError("libdiff3d.so is not built; run `python paper_2211_15634_amd/build.py` "
                       "(or __graft_entry__.build())")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
 F64, F32, BF16, BF16_RNE = 0, 1, 2, 3
 OK, EINVAL, EDTYPE, EWORKSPACE, EHIP = 0, -1, -2, -3, -4
-KERNEL_AUTO, KERNEL_NAIVE, KERNEL_ZMARCH = 0, 1, 2
+KERNEL_AUTO, KERNEL_NAIVE, KERNEL_ZMARCH, KERNEL_TB2 = 0, 1, 2, 3
 REDUCE_DOUBLES = 1025
 
 _vp, _i, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
@@ -45,6 +45,7 @@ _SIGS = {
     "diff3d_scalars": ([_i, _i, _i, _d, _d, _d, _d, _d, _dp], _i),
     "diff3d_max": ([_vp, _sz, _i, _vp, _vp], _i),
     "diff3d_step": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _vp], _i),
+    "diff3d_step2": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _vp], _i),
     "diff3d_run": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _vp, _vp, _i], _i),
     "diff3d_adjoint_workspace_bytes": ([_i, _i, _i, _i, _i, _i], _sz),
     "diff3d_adjoint_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _i, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _i,
@@ -173,6 +174,17 @@ def step(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: fl
     nz, ny, nx = T.shape
     _check(_lib.diff3d_step(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _code(T, rounding),
                             _stream(T)), "step")
+
+
+def step2(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
+          rdz: float, rounding: str = "sr") -> None:
+    """Two steps in one pass: interior of T2 = state two steps after T."""
+    _field(T, "T")
+    _field(T2, "T2", T)
+    _field(Ci, "Ci", T)
+    nz, ny, nx = T.shape
+    _check(_lib.diff3d_step2(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _code(T, rounding),
+                             _stream(T)), "step2")
 
 
 def run(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,

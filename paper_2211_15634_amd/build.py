@@ -1,7 +1,9 @@
 """Build the diff3d HIP library (libdiff3d.so) for gfx950, in-tree.
 
-    python -m paper_2211_15634_amd.build
+    python paper_2211_15634_amd/build.py
 
+(run as a script, not as a package module: importing the package loads the
+library that is about to be rebuilt).
 Compiles csrc/api.hip (which includes every kernel header) with hipcc.
 Floating-point contraction is off so that the FP64 kernels reproduce a plain
 loop bit for bit, and packed FP32 instructions are disabled.

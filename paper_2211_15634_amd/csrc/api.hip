@@ -14,6 +14,7 @@
 #include "common.hpp"
 #include "diff3d.h"
 #include "step_kernels.hpp"
+#include "tb_kernels.hpp"
 #include "util_kernels.hpp"
 
 using namespace diff3d;
@@ -214,6 +215,71 @@ int launch_zmarch(const StepArgs<DT>& a, hipStream_t st)
     return DIFF3D_EINVAL;   // configuration not instantiated (tuning override only)
 }
 
+// Two-step (temporal-blocked) configurations.
+#define DIFF3D_TB2_CFGS_8(X) X(1, 4, 4, 1) X(2, 2, 4, 1) X(1, 2, 8, 1) X(2, 2, 8, 1) X(2, 1, 8, 1) X(1, 4, 8, 1)
+#define DIFF3D_TB2_CFGS_4(X) X(1, 4, 4, 1) X(2, 2, 4, 1) X(4, 1, 8, 1) X(2, 2, 8, 1) X(4, 2, 4, 1) X(2, 1, 8, 1)
+#define DIFF3D_TB2_CFGS_2(X) X(1, 4, 4, 1) X(4, 1, 8, 1) X(4, 2, 4, 1) X(8, 1, 8, 1) X(2, 2, 8, 1) X(8, 1, 4, 1)
+
+template <int DT>
+struct Tb2Defaults;
+template <> struct Tb2Defaults<DIFF3D_F64> { static constexpr ZKey wide{2, 2, 8, 1}; static constexpr int zdef = 256; };
+template <> struct Tb2Defaults<DIFF3D_F32> { static constexpr ZKey wide{2, 2, 8, 1}; static constexpr int zdef = 128; };
+template <> struct Tb2Defaults<DIFF3D_BF16> { static constexpr ZKey wide{4, 2, 4, 1}; static constexpr int zdef = 128; };
+template <> struct Tb2Defaults<DIFF3D_BF16_RNE> { static constexpr ZKey wide{4, 2, 4, 1}; static constexpr int zdef = 128; };
+constexpr ZKey kNarrowTb2{1, 4, 4, 1};
+
+template <int DT, int V, int R, int NW, int NT>
+int launch_tb2_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req, int zdef)
+{
+    const ZPlan p = plan_tiles(a.nx, a.ny, a.nz - 2, 64 * V, R * NW, zlen_req, zdef);
+    step_tb2<DT, V, R, NW, NT != 0><<<p.blocks, 64 * NW, 0, st>>>(a, p.ntx, p.nty, p.zlen);
+    return hip_status();
+}
+
+template <int DT>
+int launch_tb2(const StepArgs<DT>& a, hipStream_t st)
+{
+    using S = typename Traits<DT>::S;
+    ZKey k = Tb2Defaults<DT>::wide;
+    env_key("DIFF3D_TCFG", k);
+    if (env_int("DIFF3D_NARROW", 0) || !vec_ok<S>(a.nx, k.V, a.T, a.T2, a.Ci)) k = kNarrowTb2;
+    const int zlen = env_int("DIFF3D_TZLEN", 0);
+    const int zdef = Tb2Defaults<DT>::zdef;
+#define DIFF3D_TRY(v, r, nw, nt) \
+    if (key_eq(k, v, r, nw, nt)) return launch_tb2_cfg<DT, v, r, nw, nt>(a, st, zlen, zdef);
+    if constexpr (sizeof(S) == 8) {
+        DIFF3D_TB2_CFGS_8(DIFF3D_TRY)
+    } else if constexpr (sizeof(S) == 4) {
+        DIFF3D_TB2_CFGS_4(DIFF3D_TRY)
+    } else {
+        DIFF3D_TB2_CFGS_2(DIFF3D_TRY)
+    }
+#undef DIFF3D_TRY
+    return DIFF3D_EINVAL;
+}
+
+// Two steps T -> T2 (T^{k+2}); SR step indices step_index and step_index+1.
+template <int DT>
+int launch_pair(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
+                double rdy, double rdz, uint64_t step_index, hipStream_t st)
+{
+    const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index);
+    return launch_tb2<DT>(a, st);
+}
+
+int pair_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
+                  double rdx, double rdy, double rdz, uint64_t step_index, hipStream_t st)
+{
+    switch (dtype) {
+    case DIFF3D_F64: return launch_pair<DIFF3D_F64>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    case DIFF3D_F32: return launch_pair<DIFF3D_F32>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    case DIFF3D_BF16: return launch_pair<DIFF3D_BF16>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    case DIFF3D_BF16_RNE:
+        return launch_pair<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    default: return DIFF3D_EDTYPE;
+    }
+}
+
 template <int DT>
 int launch_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
                 double rdy, double rdz, uint64_t step_index, hipStream_t st)
@@ -307,13 +373,25 @@ int run_loop(int dtype, void* T, void* T2, const void* Ci, int nx, int ny, int n
     const size_t fbytes = npoints(nx, ny, nz) * elem_size(dtype);
     void* a = T;
     void* b = T2;
-    for (int it = 0; it < nt; ++it) {
-        rc = step_dispatch(dtype, b, a, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step + (uint64_t)it, st);
+    // AUTO pairs steps where the two-step pass is faster: FP64 and FP32 are
+    // bound by HBM bytes, the BF16 forms by ALU work (which pairing doubles
+    // per byte), so they keep single steps.
+    const bool pairs = g_kernel == DIFF3D_KERNEL_TB2 ||
+                       (g_kernel == DIFF3D_KERNEL_AUTO && (dtype == DIFF3D_F64 || dtype == DIFF3D_F32));
+    for (int it = 0; it < nt;) {
+        // two steps in one pass unless a checkpoint falls on the state in between
+        const bool mid_ckpt = ckpt && (it + 1) % C == 0 && it + 1 <= klast;
+        const int n = (pairs && nt - it >= 2 && !mid_ckpt) ? 2 : 1;
+        if (n == 2)
+            rc = pair_dispatch(dtype, b, a, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step + (uint64_t)it, st);
+        else
+            rc = step_dispatch(dtype, b, a, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step + (uint64_t)it, st);
         if (rc) return rc;
         void* s = a;
         a = b;
         b = s;
-        const int k = it + 1;
+        it += n;
+        const int k = it;
         if (ckpt && k % C == 0 && k <= klast) {
             rc = copy_bytes(static_cast<char*>(ckpt) + (size_t)(k / C - 1) * field_stride, a, fbytes, st);
             if (rc) return rc;
@@ -510,6 +588,18 @@ int diff3d_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz,
     return rc;
 }
 
+int diff3d_step2(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
+                 double rdy, double rdz, int dtype, void* stream)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (!T2 || !T || !Ci || check_grid(nx, ny, nz)) return DIFF3D_EINVAL;
+    const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
+    if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb)) return DIFF3D_EINVAL;
+    const int rc = pair_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step, as_stream(stream));
+    g_sr_step += 2;
+    return rc;
+}
+
 int diff3d_run(void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
                double rdy, double rdz, int nt, int dtype, void* stream, void* ckpt, int ckpt_every)
 {
@@ -615,7 +705,7 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
 
 int diff3d_set_kernel(int kernel)
 {
-    if (kernel < DIFF3D_KERNEL_AUTO || kernel > DIFF3D_KERNEL_ZMARCH) return DIFF3D_EINVAL;
+    if (kernel < DIFF3D_KERNEL_AUTO || kernel > DIFF3D_KERNEL_TB2) return DIFF3D_EINVAL;
     g_kernel = kernel;
     return DIFF3D_OK;
 }

@@ -114,6 +114,16 @@ def test_step_validation():
     assert L.diff3d_step(A, B, Cc, 1 << 14, 1 << 14, 1 << 14, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F32, None) == d3.EINVAL
 
 
+def test_step2_validation():
+    L = d3._lib
+    args = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
+    assert L.diff3d_step2(None, B, Cc, *args, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_step2(A, A, Cc, *args, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_step2(A, B, A, *args, d3.F32, None) == d3.EINVAL
+    assert L.diff3d_step2(A, B, Cc, *args, 4, None) == d3.EDTYPE
+    assert L.diff3d_step2(A, B, Cc, 64, 2, 64, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F64, None) == d3.EINVAL
+
+
 def test_run_validation():
     L = d3._lib
     g = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)

@@ -27,7 +27,8 @@ SHAPES = [  # (nz, ny, nx): several tiles, ragged tails, minimal grids
 
 @pytest.fixture(autouse=True)
 def _reset(lib):
-    saved = {k: os.environ.get(k) for k in ("DIFF3D_ZCFG", "DIFF3D_ZLEN", "DIFF3D_NARROW")}
+    saved = {k: os.environ.get(k) for k in ("DIFF3D_ZCFG", "DIFF3D_ZLEN", "DIFF3D_NARROW", "DIFF3D_TCFG",
+                                             "DIFF3D_TZLEN")}
     lib.set_kernel(lib.KERNEL_AUTO)
     yield
     lib.set_kernel(lib.KERNEL_AUTO)
@@ -56,12 +57,15 @@ def _gpu_run(lib, T0, Ci, s, nt, dtype=torch.float64, rounding="sr"):
     return T, T2
 
 
+KERNELS = {"naive": 1, "zmarch": 2, "tb2": 3}
+
+
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("kernel", ["naive", "zmarch"])
+@pytest.mark.parametrize("kernel", ["naive", "zmarch", "tb2"])
 def test_fp64_bit_exact(lib, shape, kernel):
-    lib.set_kernel(lib.KERNEL_NAIVE if kernel == "naive" else lib.KERNEL_ZMARCH)
+    lib.set_kernel(KERNELS[kernel])
     T0, Ci, s = _inputs(shape)
-    for nt in (1, 6, 7):
+    for nt in (1, 2, 6, 7):
         ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
         T, _ = _gpu_run(lib, T0, Ci, s, nt)
         np.testing.assert_array_equal(to_host(T), ref)
@@ -98,6 +102,79 @@ def test_zmarch_configs(lib, dtype, cfg, zlen):
         lib.set_sr_seed(77, 0)
         R, _ = _gpu_run(lib, T0, Ci, s, 4, dtype=tdt, rounding=rounding)
         assert torch.equal(T, R)
+
+
+def _tb2_cases():
+    out = []
+    for name, size in (("f64", 8), ("f32", 4), ("bf16", 2), ("bf16_rne", 2)):
+        for cfg in instantiated_configs("TB2", size):
+            for zlen in (0, 1, 3):
+                out.append((name, cfg, zlen))
+    return out
+
+
+@pytest.mark.parametrize("dtype,cfg,zlen", _tb2_cases())
+def test_tb2_configs(lib, dtype, cfg, zlen):
+    """Every instantiated two-step configuration and several z-chunk lengths:
+    FP64 bit-identical to the oracle, other dtypes bit-identical to single
+    steps of the naive kernel (same operation order, same random draws)."""
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "bf16_rne": torch.bfloat16}[dtype]
+    rounding = "rne" if dtype == "bf16_rne" else "sr"
+    shape = (14, 37, 192)
+    T0, Ci, s = _inputs(shape, seed=sum(cfg) + zlen + 50)
+    os.environ["DIFF3D_TZLEN"] = str(zlen)
+    os.environ["DIFF3D_TCFG"] = ",".join(str(c) for c in cfg)
+    lib.set_kernel(lib.KERNEL_TB2)
+    lib.set_sr_seed(78, 0)
+    T, _ = _gpu_run(lib, T0, Ci, s, 5, dtype=tdt, rounding=rounding)
+    if dtype == "f64":
+        ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 5)
+        np.testing.assert_array_equal(to_host(T), ref)
+    else:
+        lib.set_kernel(lib.KERNEL_NAIVE)
+        lib.set_sr_seed(78, 0)
+        R, _ = _gpu_run(lib, T0, Ci, s, 5, dtype=tdt, rounding=rounding)
+        assert torch.equal(T, R)
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 3), (4, 5, 6), (5, 70, 33), (9, 3, 130), (20, 66, 64)])
+def test_tb2_small_and_ragged(lib, shape):
+    """Two-step passes on grids with one or two interior planes, ragged x
+    and y tiles and z-chunks shorter than the halo."""
+    os.environ["DIFF3D_TZLEN"] = "1"
+    lib.set_kernel(lib.KERNEL_TB2)
+    T0, Ci, s = _inputs(shape, seed=3)
+    for nt in (2, 4, 9):
+        ref = oracle.forward(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
+        T, _ = _gpu_run(lib, T0, Ci, s, nt)
+        np.testing.assert_array_equal(to_host(T), ref)
+    os.environ.pop("DIFF3D_TZLEN")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "bf16_rne"])
+def test_step2_equals_two_steps(lib, dtype):
+    """diff3d_step2 writes the interior of T2 with the state two steps on,
+    bit-identical to two diff3d_step calls, and leaves T2's boundary alone."""
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "bf16_rne": torch.bfloat16}[dtype]
+    rounding = "rne" if dtype == "bf16_rne" else "sr"
+    shape = (19, 34, 256)
+    T0, Ci, s = _inputs(shape, seed=9)
+    sc = (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+    T, C = to_dev(T0, tdt), to_dev(Ci, tdt)
+    lib.set_sr_seed(5, 40)
+    M = T.clone()
+    lib.step(M, T, C, *sc, rounding=rounding)
+    R = M.clone()
+    lib.step(R, M, C, *sc, rounding=rounding)
+    lib.set_sr_seed(5, 40)
+    Q = torch.full_like(T, float("nan"))
+    b = torch.from_numpy(~interior_mask(shape)).cuda()
+    Q[b] = -3.0
+    lib.step2(Q, T, C, *sc, rounding=rounding)
+    torch.cuda.synchronize()
+    m = torch.from_numpy(interior_mask(shape)).cuda()
+    assert torch.equal(Q[m], R[m])
+    assert torch.all(Q[b] == -3.0)
 
 
 def test_narrow_fallback_ragged_rows(lib):
@@ -172,12 +249,12 @@ def test_kernels_agree_bitwise(lib, dtype, shape):
     rounding = "rne" if dtype == "bf16_rne" else "sr"
     T0, Ci, s = _inputs(shape)
     outs = []
-    for kernel in (lib.KERNEL_NAIVE, lib.KERNEL_ZMARCH):
+    for kernel in (lib.KERNEL_NAIVE, lib.KERNEL_ZMARCH, lib.KERNEL_TB2):
         lib.set_kernel(kernel)
         lib.set_sr_seed(1234, 0)
         T, _ = _gpu_run(lib, T0, Ci, s, 5, dtype=tdt, rounding=rounding)
         outs.append(T)
-    assert torch.equal(outs[0], outs[1])
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
 
 
 def test_deterministic_and_seeded(lib):
@@ -215,7 +292,9 @@ def test_run_semantics(lib):
     assert torch.equal(T1, T2d)
 
 
-def test_checkpoints_written(lib):
+@pytest.mark.parametrize("kernel", ["zmarch", "tb2"])
+def test_checkpoints_written(lib, kernel):
+    lib.set_kernel(KERNELS[kernel])
     shape = (12, 14, 64)
     T0, Ci, s = _inputs(shape)
     nt, C = 23, 5
