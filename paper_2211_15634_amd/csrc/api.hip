@@ -82,6 +82,7 @@ StepArgs<DT> make_step_args(void* T2, const void* T, const void* Ci, int nx, int
     a.T2 = static_cast<S*>(T2);
     a.T = static_cast<const S*>(T);
     a.Ci = static_cast<const S*>(Ci);
+    a.Tmid = nullptr;
     a.nx = nx;
     a.ny = ny;
     a.nz = nz;
@@ -228,15 +229,15 @@ template <> struct Tb2Defaults<DIFF3D_BF16> { static constexpr ZKey wide{4, 2, 4
 template <> struct Tb2Defaults<DIFF3D_BF16_RNE> { static constexpr ZKey wide{4, 2, 4, 1}; static constexpr int zdef = 128; };
 constexpr ZKey kNarrowTb2{1, 4, 4, 1};
 
-template <int DT, int V, int R, int NW, int NT>
+template <int DT, int V, int R, int NW, int NT, bool MID>
 int launch_tb2_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req, int zdef)
 {
     const ZPlan p = plan_tiles(a.nx, a.ny, a.nz - 2, 64 * V, R * NW, zlen_req, zdef);
-    step_tb2<DT, V, R, NW, NT != 0><<<p.blocks, 64 * NW, 0, st>>>(a, p.ntx, p.nty, p.zlen);
+    step_tb2<DT, V, R, NW, NT != 0, MID><<<p.blocks, 64 * NW, 0, st>>>(a, p.ntx, p.nty, p.zlen);
     return hip_status();
 }
 
-template <int DT>
+template <int DT, bool MID>
 int launch_tb2(const StepArgs<DT>& a, hipStream_t st)
 {
     using S = typename Traits<DT>::S;
@@ -246,7 +247,7 @@ int launch_tb2(const StepArgs<DT>& a, hipStream_t st)
     const int zlen = env_int("DIFF3D_TZLEN", 0);
     const int zdef = Tb2Defaults<DT>::zdef;
 #define DIFF3D_TRY(v, r, nw, nt) \
-    if (key_eq(k, v, r, nw, nt)) return launch_tb2_cfg<DT, v, r, nw, nt>(a, st, zlen, zdef);
+    if (key_eq(k, v, r, nw, nt)) return launch_tb2_cfg<DT, v, r, nw, nt, MID>(a, st, zlen, zdef);
     if constexpr (sizeof(S) == 8) {
         DIFF3D_TB2_CFGS_8(DIFF3D_TRY)
     } else if constexpr (sizeof(S) == 4) {
@@ -264,7 +265,27 @@ int launch_pair(void* T2, const void* T, const void* Ci, int nx, int ny, int nz,
                 double rdy, double rdz, uint64_t step_index, hipStream_t st)
 {
     const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index);
-    return launch_tb2<DT>(a, st);
+    return launch_tb2<DT, false>(a, st);
+}
+
+// Two steps T -> Tmid (T^{k+1}) and T2 (T^{k+2}), interior points of both.
+template <int DT>
+int launch_pair_mid(void* T2, void* Tmid, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
+                    double dt, double rdx, double rdy, double rdz, hipStream_t st)
+{
+    StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, 0);
+    a.Tmid = static_cast<typename Traits<DT>::S*>(Tmid);
+    return launch_tb2<DT, true>(a, st);
+}
+
+int pair_mid_dispatch(int dtype, void* T2, void* Tmid, const void* T, const void* Ci, int nx, int ny, int nz,
+                      double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+{
+    switch (dtype) {
+    case DIFF3D_F64: return launch_pair_mid<DIFF3D_F64>(T2, Tmid, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    case DIFF3D_F32: return launch_pair_mid<DIFF3D_F32>(T2, Tmid, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    default: return DIFF3D_EDTYPE;
+    }
 }
 
 int pair_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
@@ -685,12 +706,23 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
         const int s = j * C;
         const int e = (s + C < nt) ? s + C : nt;
         const void* base = j == 0 ? T0 : slot(j);
-        // states T_{s+1} .. T_{e-1} into seg(0) .. seg(e-s-2)
+        // states T_{s+1} .. T_{e-1} into seg(0) .. seg(e-s-2), two at a time
+        // where possible (one pass writing both the intermediate and the
+        // second state), the two-step kernel unless single steps are selected
         const void* src = base;
-        for (int k = s; k < e - 1; ++k) {
-            rc = step_dispatch(dtype, seg(k - s), src, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, 0, st);
+        const bool pairs = g_kernel == DIFF3D_KERNEL_AUTO || g_kernel == DIFF3D_KERNEL_TB2;
+        for (int k = s; k < e - 1;) {
+            if (pairs && k + 2 <= e - 1) {
+                rc = pair_mid_dispatch(dtype, seg(k - s + 1), seg(k - s), src, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz,
+                                       st);
+                src = seg(k - s + 1);
+                k += 2;
+            } else {
+                rc = step_dispatch(dtype, seg(k - s), src, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, 0, st);
+                src = seg(k - s);
+                k += 1;
+            }
             if (rc) return rc;
-            src = seg(k - s);
         }
         for (int k = e - 1; k >= s; --k) {
             const void* Tk = k == s ? base : seg(k - s - 1);

@@ -19,6 +19,7 @@ struct StepArgs {
     S* __restrict__ T2;
     const S* __restrict__ T;
     const S* __restrict__ Ci;
+    S* __restrict__ Tmid;    // two-step kernel only: optional output of the intermediate state
     int nx, ny, nz;
     C lam, dt, cx, cy, cz;
     SrState sr;

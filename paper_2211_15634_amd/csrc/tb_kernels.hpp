@@ -24,7 +24,10 @@ namespace diff3d {
 // ring columns by waves WXL (left) and WXR (right); those waves also load the
 // second ring of T^k and the four corners of the first.  One LDS-only
 // barrier per plane; loads run one plane ahead.
-template <int DT, int V, int R, int NW, bool NT>
+// With MID, the intermediate state of the workgroup's own planes is also
+// stored (interior points) into a.Tmid: the reverse sweep recomputes every
+// state of a checkpoint segment this way at two field passes per step.
+template <int DT, int V, int R, int NW, bool NT, bool MID>
 __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int nty, int zlen)
 {
     using Tr = Traits<DT>;
@@ -206,6 +209,22 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
                 }
                 u2[r][v] = u;
                 lB[bB][1 + wave * R + r][1 + lane * V + v] = u;
+            }
+            if constexpr (MID) {
+                // own planes only (the halo planes belong to the neighbouring chunks)
+                if (p >= zb && p < ze && xin && y >= 1 && y <= ny - 2 && zin) {
+                    const size_t i0 = (size_t)xl + sy * y + sz * p;
+                    S st[V];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) st[v] = Tr::store(u2[r][v], 0);   // exact: u2 is already rounded
+                    if (xl >= 1 && xl + V - 1 <= nx - 2) {
+                        vstore<S, V>(a.Tmid + i0, st);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v)
+                            if (xl + v >= 1 && xl + v <= nx - 2) a.Tmid[i0 + v] = st[v];
+                    }
+                }
             }
         }
         if (yrole) {

@@ -51,9 +51,9 @@ def _adjoint(lib, T0, Ci, g, s, nt, C, dtype=torch.float64, ready=False):
 
 @pytest.mark.parametrize("shape,nt,C", [((6, 5, 7), 5, 2), ((19, 37, 131), 9, 4), ((21, 20, 128), 13, 5),
                                         ((3, 3, 3), 4, 3), ((8, 70, 64), 7, 1), ((9, 9, 192), 6, 10)])
-@pytest.mark.parametrize("kernel", ["naive", "zmarch"])
+@pytest.mark.parametrize("kernel", ["naive", "zmarch", "auto"])
 def test_fp64_matches_oracle_bitwise(lib, shape, nt, C, kernel):
-    lib.set_kernel(lib.KERNEL_NAIVE if kernel == "naive" else lib.KERNEL_ZMARCH)
+    lib.set_kernel({"naive": lib.KERNEL_NAIVE, "zmarch": lib.KERNEL_ZMARCH, "auto": lib.KERNEL_AUTO}[kernel])
     T0, Ci, g, s = _inputs(shape)
     rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
     for ready in (False, True):
