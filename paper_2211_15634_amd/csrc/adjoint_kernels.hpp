@@ -24,6 +24,7 @@ struct AdjArgs {
     const S* __restrict__ lin;    // lambda_{k+1}
     const S* __restrict__ Ci;
     const S* __restrict__ Tk;     // forward state T_k
+    const S* __restrict__ Tk1;    // two-step kernel only: forward state T_{k-1}
     S* __restrict__ gCi;          // accumulated in place (interior points)
     int nx, ny, nz;
     C dtlam, cx, cy, cz;

@@ -117,7 +117,7 @@ struct ZPlan {
 // least kMinBlocks workgroups.
 constexpr long kMinBlocks = 512;
 
-inline ZPlan plan_tiles(int nx, int ny, int nzout, int TX, int TY, int zlen_req, int zdef)
+inline ZPlan plan_tiles(int nx, int ny, int nzout, int TX, int TY, int zlen_req, int zdef, long min_blocks = kMinBlocks)
 {
     ZPlan p;
     p.ntx = (nx + TX - 1) / TX;
@@ -126,7 +126,7 @@ inline ZPlan plan_tiles(int nx, int ny, int nzout, int TX, int TY, int zlen_req,
     int zlen = zlen_req;
     if (zlen <= 0) {
         long nch = (nzout + zdef - 1) / zdef;
-        const long need = (kMinBlocks + tiles - 1) / tiles;
+        const long need = (min_blocks + tiles - 1) / tiles;
         if (nch < need) nch = need;
         zlen = (int)((nzout + nch - 1) / nch);
         if (zlen < 4) zlen = 4;
@@ -435,6 +435,7 @@ AdjArgs<DT> make_adj_args(void* lout, const void* lin, const void* Ci, const voi
     a.lin = static_cast<const S*>(lin);
     a.Ci = static_cast<const S*>(Ci);
     a.Tk = static_cast<const S*>(Tk);
+    a.Tk1 = nullptr;
     a.gCi = static_cast<S*>(gCi);
     a.nx = nx;
     a.ny = ny;
@@ -489,6 +490,63 @@ int launch_adj(void* lout, const void* lin, const void* Ci, const void* Tk, void
     }
 #undef DIFF3D_TRY
     return DIFF3D_EINVAL;
+}
+
+// Two adjoint steps per pass.
+#define DIFF3D_ADJ2_CFGS_8(X) X(1, 1, 8) X(1, 2, 8) X(1, 2, 4) X(2, 1, 8) X(1, 4, 4)
+#define DIFF3D_ADJ2_CFGS_4(X) X(1, 1, 8) X(2, 1, 8) X(1, 4, 4) X(1, 2, 8) X(2, 2, 4) X(4, 1, 8)
+
+template <int DT>
+struct Adj2Defaults;
+template <> struct Adj2Defaults<DIFF3D_F64> { static constexpr ZKey wide{1, 2, 8, 0}; static constexpr int zdef = 64; };
+template <> struct Adj2Defaults<DIFF3D_F32> { static constexpr ZKey wide{1, 4, 4, 0}; static constexpr int zdef = 32; };
+constexpr ZKey kNarrowAdj2{1, 2, 8, 0};
+
+template <int DT, int V, int R, int NW>
+int launch_adj2_cfg(const AdjArgs<DT>& a, hipStream_t st, int zlen_req, int zdef)
+{
+    // one workgroup of this register-heavy kernel per CU is enough: allow
+    // chunks as long as zdef down to 256 workgroups
+    const ZPlan p = plan_tiles(a.nx, a.ny, a.nz, 64 * V, R * NW, zlen_req, zdef, 256);
+    adj_tb2<DT, V, R, NW><<<p.blocks, 64 * NW, 0, st>>>(a, p.ntx, p.nty, p.zlen);
+    return hip_status();
+}
+
+template <int DT>
+int launch_adj2(void* lout, const void* lin, const void* Ci, const void* Tk, const void* Tk1, void* gCi, int nx,
+                int ny, int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+{
+    using S = typename Traits<DT>::S;
+    AdjArgs<DT> a = make_adj_args<DT>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz);
+    a.Tk1 = static_cast<const S*>(Tk1);
+    ZKey k = Adj2Defaults<DT>::wide;
+    env_key("DIFF3D_BCFG", k);
+    const bool aligned = (uintptr_t)lout % 16 == 0 && (uintptr_t)lin % 16 == 0 && (uintptr_t)Ci % 16 == 0 &&
+                         (uintptr_t)Tk % 16 == 0 && (uintptr_t)Tk1 % 16 == 0 && (uintptr_t)gCi % 16 == 0;
+    if (k.V > 1 && (env_int("DIFF3D_NARROW", 0) || nx % k.V != 0 || !aligned)) k = kNarrowAdj2;
+    const int zlen = env_int("DIFF3D_BZLEN", 0);
+    const int zdef = Adj2Defaults<DT>::zdef;
+#define DIFF3D_TRY(v, r, nw) \
+    if (k.V == v && k.R == r && k.NW == nw) return launch_adj2_cfg<DT, v, r, nw>(a, st, zlen, zdef);
+    if constexpr (sizeof(S) == 8) {
+        DIFF3D_ADJ2_CFGS_8(DIFF3D_TRY)
+    } else {
+        DIFF3D_ADJ2_CFGS_4(DIFF3D_TRY)
+    }
+#undef DIFF3D_TRY
+    return DIFF3D_EINVAL;
+}
+
+int adj2_dispatch(int dtype, void* lout, const void* lin, const void* Ci, const void* Tk, const void* Tk1, void* gCi,
+                  int nx, int ny, int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+{
+    switch (dtype) {
+    case DIFF3D_F64:
+        return launch_adj2<DIFF3D_F64>(lout, lin, Ci, Tk, Tk1, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    case DIFF3D_F32:
+        return launch_adj2<DIFF3D_F32>(lout, lin, Ci, Tk, Tk1, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    default: return DIFF3D_EDTYPE;
+    }
 }
 
 int adj_dispatch(int dtype, void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny,
@@ -701,6 +759,15 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
         if (rc) return rc;
     }
 
+    // adjoint launches (two steps per launch inside a segment where enabled);
+    // lambda alternates between gT0 and W so that the last launch writes gT0
+    const bool apairs = g_kernel == DIFF3D_KERNEL_AUTO || g_kernel == DIFF3D_KERNEL_TB2;
+    long nlaunch = 0;
+    for (int j = nck - 1; j >= 0; --j) {
+        const int len = ((j * C + C < nt) ? j * C + C : nt) - j * C;
+        nlaunch += apairs ? (len + 1) / 2 : len;
+    }
+    long launch = 0;
     const void* lin = gTnt;
     for (int j = nck - 1; j >= 0; --j) {
         const int s = j * C;
@@ -724,12 +791,20 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
             }
             if (rc) return rc;
         }
-        for (int k = e - 1; k >= s; --k) {
-            const void* Tk = k == s ? base : seg(k - s - 1);
-            void* out = (k % 2 == 0) ? gT0 : W;
-            rc = adj_dispatch(dtype, out, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+        auto state = [&](int k) -> const void* { return k == s ? base : seg(k - s - 1); };
+        for (int k = e - 1; k >= s;) {
+            void* out = ((nlaunch - 1 - launch) % 2 == 0) ? gT0 : W;
+            if (apairs && k - 1 >= s) {
+                rc = adj2_dispatch(dtype, out, lin, Ci, state(k), state(k - 1), gCi, nx, ny, nz, lam, dt, rdx, rdy,
+                                   rdz, st);
+                k -= 2;
+            } else {
+                rc = adj_dispatch(dtype, out, lin, Ci, state(k), gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+                k -= 1;
+            }
             if (rc) return rc;
             lin = out;
+            ++launch;
         }
     }
     return DIFF3D_OK;

@@ -327,3 +327,404 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
 }
 
 }  // namespace diff3d
+
+#include "adjoint_kernels.hpp"
+
+namespace diff3d {
+
+// Two adjoint steps per pass: from lambda_{k+1} (a.lin), T_k (a.Tk) and
+// T_{k-1} (a.Tk1) to lambda_{k-1} (a.lout), adding both steps' terms to gCi
+// in the order of two single adjoint steps (bit-identical for FP64/FP32).
+// Per plane p the workgroup
+//   A. computes lambda_k(p) on the tile and on the one-point ring (no
+//      corners) from mu_{k+1} = dt*lam*Ci*lambda_{k+1} staged in LDS with a
+//      two-point ring, then mu_k = dt*lam*Ci*lambda_k (LDS, registers), and
+//      the partial gCi(p) + dt*lam*lambda_{k+1}*Lap(T_k) on the tile;
+//   B. computes lambda_{k-1}(p-1) = lambda_k + Lap(mu_k) on the tile (every
+//      point, boundary included) and gCi(p-1) += dt*lam*lambda_k*Lap(T_{k-1})
+//      on interior points, and stores both.
+// Outputs cover planes zb .. ze-1 of all nz planes; mu is 0 outside the
+// interior.  Ring roles and the pipeline follow step_tb2.
+template <int DT, int V, int R, int NW>
+__global__ __launch_bounds__(64 * NW) void adj_tb2(AdjArgs<DT> a, int ntx, int nty, int zlen)
+{
+    using Tr = Traits<DT>;
+    using S = typename Tr::S;
+    using C = typename Tr::C;
+    constexpr int TX = 64 * V, TY = R * NW;
+    constexpr int WYL = 0, WYH = NW - 1, WXL = 1, WXR = 2;
+    static_assert(NW >= 4, "the four ring roles need four distinct waves");
+    static_assert(TY + 2 <= 64, "ring columns are held one point per lane");
+    __shared__ C lM1[2][TY + 4][TX + 4];   // mu_{k+1}, origin (y0 - 2, x0 - 2)
+    __shared__ C lTA[2][TY + 2][TX + 2];   // T_k, origin (y0 - 1, x0 - 1)
+    __shared__ C lM0[2][TY + 2][TX + 2];   // mu_k
+    __shared__ C lTB[2][TY + 2][TX + 2];   // T_{k-1}
+
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = (int)(t % (unsigned)ntx);
+    const int rest = (int)(t / (unsigned)ntx);
+    const int ty = rest % nty, tz = rest / nty;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int zb = tz * zlen;                    // output planes zb .. ze-1
+    const int ze = min(nz, zb + zlen);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int xl = x0 + lane * V;
+    const bool xin = xl < nx;
+    const int yw = y0 + wave * R;
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+
+    const bool yrole = wave == WYL || wave == WYH;
+    const int yr1 = wave == WYL ? y0 - 1 : y0 + TY;
+    const int yr2 = wave == WYL ? y0 - 2 : y0 + TY + 1;
+    const int ay1 = wave == WYL ? 1 : TY + 2;
+    const int ay2 = wave == WYL ? 0 : TY + 3;
+    const int by1 = wave == WYL ? 0 : TY + 1;
+    const bool xrole = (wave == WXL || wave == WXR) && lane < TY + 2;
+    const int xc1 = wave == WXL ? x0 - 1 : x0 + TX;
+    const int xc2 = wave == WXL ? x0 - 2 : x0 + TX + 1;
+    const int ax1 = wave == WXL ? 1 : TX + 2;
+    const int ax2 = wave == WXL ? 0 : TX + 3;
+    const int bx1 = wave == WXL ? 0 : TX + 1;
+    const int yx = y0 - 1 + lane;
+    const bool xmid = lane >= 1 && lane <= TY;
+
+    const bool yin1 = yrole && xin && yr1 >= 0 && yr1 < ny;
+    const bool yin2 = yrole && xin && yr2 >= 0 && yr2 < ny;
+    const bool xin1 = xrole && xc1 >= 0 && xc1 < nx && yx >= 0 && yx < ny;
+    const bool xin2 = xrole && xmid && xc2 >= 0 && xc2 < nx && yx >= 0 && yx < ny;
+
+    using Rows = C[R][V];
+    using Vec = C[V];
+    auto inner = [&](int x, int y, int z) __attribute__((always_inline)) {
+        return x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2 && z >= 1 && z <= nz - 2;
+    };
+    // V points from (x, y, z) of one field, zero outside the grid
+    auto vld = [&](const S* base, int x, int y, int z, Vec& dst, bool ok) __attribute__((always_inline)) {
+        if (ok && z >= 0 && z < nz) {
+            S raw[V];
+            vload<S, V>(base + (size_t)x + sy * y + sz * z, raw);
+#pragma unroll
+            for (int v = 0; v < V; ++v) dst[v] = Tr::load(raw[v]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) dst[v] = C(0);
+        }
+    };
+    auto sld = [&](const S* base, int x, int y, int z, C& dst, bool ok) __attribute__((always_inline)) {
+        dst = (ok && z >= 0 && z < nz) ? Tr::load(base[(size_t)x + sy * y + sz * z]) : C(0);
+    };
+    // mu = dt*lam*Ci*lambda on interior points, 0 elsewhere
+    auto muv = [&](int x, int y, int z, const Vec& ci, const Vec& l, Vec& m) __attribute__((always_inline)) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) m[v] = inner(x + v, y, z) ? a.dtlam * ci[v] * l[v] : C(0);
+    };
+
+    // ---- register state; index 0 = oldest plane
+    Rows m1[4];     // tile mu_{k+1} at p-1 .. p+2
+    Rows l1[3];     // tile lambda_{k+1} at p .. p+2
+    Rows c1[3];     // tile Ci at p .. p+2
+    Rows ta[4];     // tile T_k at p-1 .. p+2
+    Rows tb[4];     // tile T_{k-1} at p-2 .. p+1
+    Rows g[2];      // tile gCi at p, p+1
+    Rows g1m;       // tile gCi + step-k term at p-1
+    Rows m0[3];     // tile mu_k at p-2 .. p
+    Rows lkm;       // tile lambda_k at p-1
+    Vec ym1[4], yl1[3], yc1[3], yta[2], ytb[2], ym2[2];   // y roles: ring row
+    C xm1[4], xl1[3], xc1v[3], xta[2], xtb[2], xm2[2];    // x roles: ring column (lanes 0..TY+1)
+
+    auto zero_rows = [&](Rows& r_) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < V; ++v) r_[r][v] = C(0);
+    };
+    auto copy_rows = [&](Rows& d, const Rows& s_) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < V; ++v) d[r][v] = s_[r][v];
+    };
+    auto copy_vec = [&](Vec& d, const Vec& s_) __attribute__((always_inline)) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) d[v] = s_[v];
+    };
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        zero_rows(m1[i]);
+        zero_rows(ta[i]);
+        zero_rows(tb[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        zero_rows(l1[i]);
+        zero_rows(c1[i]);
+        zero_rows(m0[i]);
+    }
+    zero_rows(g[0]);
+    zero_rows(g[1]);
+    zero_rows(g1m);
+    zero_rows(lkm);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        for (int i = 0; i < 4; ++i) ym1[i][v] = C(0);
+        for (int i = 0; i < 3; ++i) yl1[i][v] = yc1[i][v] = C(0);
+        for (int i = 0; i < 2; ++i) yta[i][v] = ytb[i][v] = ym2[i][v] = C(0);
+    }
+    for (int i = 0; i < 4; ++i) xm1[i] = C(0);
+    for (int i = 0; i < 3; ++i) xl1[i] = xc1v[i] = C(0);
+    for (int i = 0; i < 2; ++i) xta[i] = xtb[i] = xm2[i] = C(0);
+
+    // lambda_{k+1}, Ci and mu_{k+1} of plane z: tile and first ring;
+    // second-ring mu_{k+1} into (r2y, r2x)
+    auto load_lam = [&](int z, Rows& m, Rows& l, Rows& c, Vec& ym, Vec& yl, Vec& yc, C& xm, C& xl_, C& xc,
+                        Vec& r2y, C& r2x) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool ok = xin && yw + r < ny;
+            vld(a.lin, xl, yw + r, z, l[r], ok);
+            vld(a.Ci, xl, yw + r, z, c[r], ok);
+            muv(xl, yw + r, z, c[r], l[r], m[r]);
+        }
+        vld(a.lin, xl, yr1, z, yl, yin1);
+        vld(a.Ci, xl, yr1, z, yc, yin1);
+        muv(xl, yr1, z, yc, yl, ym);
+        sld(a.lin, xc1, yx, z, xl_, xin1);
+        sld(a.Ci, xc1, yx, z, xc, xin1);
+        xm = inner(xc1, yx, z) ? a.dtlam * xc * xl_ : C(0);
+        Vec l2, c2;
+        vld(a.lin, xl, yr2, z, l2, yin2);
+        vld(a.Ci, xl, yr2, z, c2, yin2);
+        muv(xl, yr2, z, c2, l2, r2y);
+        C l2x, c2x;
+        sld(a.lin, xc2, yx, z, l2x, xin2);
+        sld(a.Ci, xc2, yx, z, c2x, xin2);
+        r2x = inner(xc2, yx, z) ? a.dtlam * c2x * l2x : C(0);
+    };
+    // a forward state of plane z: tile and first ring (no corners)
+    auto load_state = [&](const S* base, int z, Rows& tile, Vec& yv, C& xv) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) vld(base, xl, yw + r, z, tile[r], xin && yw + r < ny);
+        vld(base, xl, yr1, z, yv, yin1);
+        sld(base, xc1, yx, z, xv, xin1 && xmid);
+    };
+    auto load_g = [&](int z, Rows& dst) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) vld(a.gCi, xl, yw + r, z, dst[r], xin && yw + r < ny);
+    };
+    auto stage_m1 = [&](int buf, const Rows& m, const Vec& ym, C xm, const Vec& r2y, C r2x)
+        __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < V; ++v) lM1[buf][2 + wave * R + r][2 + lane * V + v] = m[r][v];
+        if (yrole) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                lM1[buf][ay1][2 + lane * V + v] = ym[v];
+                lM1[buf][ay2][2 + lane * V + v] = r2y[v];
+            }
+        }
+        if (xrole) {
+            lM1[buf][1 + lane][ax1] = xm;
+            if (xmid) lM1[buf][1 + lane][ax2] = r2x;
+        }
+    };
+    auto stage_ring1 = [&](C (&L)[2][TY + 2][TX + 2], int buf, const Rows& tile, const Vec& yv, C xv)
+        __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < V; ++v) L[buf][1 + wave * R + r][1 + lane * V + v] = tile[r][v];
+        if (yrole)
+#pragma unroll
+            for (int v = 0; v < V; ++v) L[buf][by1][1 + lane * V + v] = yv[v];
+        if (xrole && xmid) L[buf][lane][bx1] = xv;
+    };
+
+    const int p0 = zb - 1;
+    // prologue: mu_{k+1} at p0-1 .. p0+1 (plane p0 staged with both rings),
+    // second ring of p0+1, T_k at p0-1 .. p0+1 (p0 staged), T_{k-1} at
+    // p0-1, p0, gCi at p0
+    {
+        Vec r2y;
+        C r2x;
+        Rows ldum, cdum;
+        Vec yldum, ycdum;
+        C xldum, xcdum;
+        load_lam(p0 - 1, m1[0], ldum, cdum, ym1[0], yldum, ycdum, xm1[0], xldum, xcdum, r2y, r2x);
+        load_lam(p0, m1[1], l1[0], c1[0], ym1[1], yl1[0], yc1[0], xm1[1], xl1[0], xc1v[0], r2y, r2x);
+        stage_m1(0, m1[1], ym1[1], xm1[1], r2y, r2x);
+        load_lam(p0 + 1, m1[2], l1[1], c1[1], ym1[2], yl1[1], yc1[1], xm1[2], xl1[1], xc1v[1], ym2[0], xm2[0]);
+        Vec ydum;
+        C xdum;
+        load_state(a.Tk, p0 - 1, ta[0], ydum, xdum);
+        load_state(a.Tk, p0, ta[1], yta[0], xta[0]);
+        stage_ring1(lTA, 0, ta[1], yta[0], xta[0]);
+        load_state(a.Tk, p0 + 1, ta[2], yta[1], xta[1]);
+        load_state(a.Tk1, p0 - 1, tb[1], ydum, xdum);
+        load_state(a.Tk1, p0, tb[2], ytb[0], xtb[0]);
+        load_g(p0, g[0]);
+    }
+
+    int b = 0;
+    for (int p = p0; p <= ze; ++p) {
+        const bool more = p + 1 <= ze;
+        // 1. loads one plane ahead
+        if (more) {
+            load_lam(p + 2, m1[3], l1[2], c1[2], ym1[3], yl1[2], yc1[2], xm1[3], xl1[2], xc1v[2], ym2[1], xm2[1]);
+            load_state(a.Tk, p + 2, ta[3], yta[0], xta[0]);   // ring T_k of p+2 (index 0 is free)
+            load_state(a.Tk1, p + 1, tb[3], ytb[1], xtb[1]);
+            load_g(p + 1, g[1]);
+        }
+        lds_barrier();
+        // 2. stage mu_{k+1} and T_k of plane p+1, T_{k-1} of plane p
+        if (more) {
+            stage_m1(b ^ 1, m1[2], ym1[2], xm1[2], ym2[0], xm2[0]);
+            stage_ring1(lTA, b ^ 1, ta[2], yta[1], xta[1]);
+        }
+        stage_ring1(lTB, b, tb[2], ytb[0], xtb[0]);
+
+        // A. lambda_k(p) and mu_k(p) on tile and ring; partial gCi on the tile
+        const bool pin = p >= 0 && p <= nz - 1;
+        Rows lk, mk, g1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = yw + r;
+            const int rowA = 2 + wave * R + r, rowB = 1 + wave * R + r;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int x = xl + v, colA = 2 + lane * V + v, colB = 1 + lane * V + v;
+                const C mxm = v > 0 ? m1[1][r][v - 1] : lM1[b][rowA][colA - 1];
+                const C mxp = v < V - 1 ? m1[1][r][v + 1] : lM1[b][rowA][colA + 1];
+                const C mym = r > 0 ? m1[1][r - 1][v] : lM1[b][rowA - 1][colA];
+                const C myp = r < R - 1 ? m1[1][r + 1][v] : lM1[b][rowA + 1][colA];
+                const C lm = lap7<DT>(m1[1][r][v], mxm, mxp, mym, myp, m1[0][r][v], m1[2][r][v], a);
+                const C l = pin ? Tr::load(Tr::store(l1[0][r][v] + lm, 0)) : C(0);
+                lk[r][v] = l;
+                mk[r][v] = (pin && inner(x, y, p)) ? a.dtlam * c1[0][r][v] * l : C(0);
+                lM0[b][rowB][colB] = mk[r][v];
+                g1[r][v] = g[0][r][v];
+                if (xin && inner(x, y, p)) {
+                    const C txm = v > 0 ? ta[1][r][v - 1] : lTA[b][rowB][colB - 1];
+                    const C txp = v < V - 1 ? ta[1][r][v + 1] : lTA[b][rowB][colB + 1];
+                    const C tym = r > 0 ? ta[1][r - 1][v] : lTA[b][rowB - 1][colB];
+                    const C typ = r < R - 1 ? ta[1][r + 1][v] : lTA[b][rowB + 1][colB];
+                    const C ltk = lap7<DT>(ta[1][r][v], txm, txp, tym, typ, ta[0][r][v], ta[2][r][v], a);
+                    g1[r][v] = Tr::load(Tr::store(g[0][r][v] + a.dtlam * l1[0][r][v] * ltk, 0));
+                }
+            }
+        }
+        if (yrole) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int x = xl + v, colA = 2 + lane * V + v;
+                const C mxm = v > 0 ? ym1[1][v - 1] : lM1[b][ay1][colA - 1];
+                const C mxp = v < V - 1 ? ym1[1][v + 1] : lM1[b][ay1][colA + 1];
+                const C lm = lap7<DT>(ym1[1][v], mxm, mxp, lM1[b][ay1 - 1][colA], lM1[b][ay1 + 1][colA], ym1[0][v],
+                                      ym1[2][v], a);
+                const C l = pin ? Tr::load(Tr::store(yl1[0][v] + lm, 0)) : C(0);
+                lM0[b][by1][1 + lane * V + v] = (pin && inner(x, yr1, p)) ? a.dtlam * yc1[0][v] * l : C(0);
+            }
+        }
+        if (xrole && xmid) {
+            const C lm = lap7<DT>(xm1[1], lM1[b][1 + lane][ax1 - 1], lM1[b][1 + lane][ax1 + 1], lM1[b][lane][ax1],
+                                  lM1[b][2 + lane][ax1], xm1[0], xm1[2], a);
+            const C l = pin ? Tr::load(Tr::store(xl1[0] + lm, 0)) : C(0);
+            lM0[b][lane][bx1] = (pin && inner(xc1, yx, p)) ? a.dtlam * xc1v[0] * l : C(0);
+        }
+
+        // B. lambda_{k-1}(p-1) and gCi(p-1) on the tile
+        if (p >= zb + 1) {
+            const int q = p - 1;
+            const int bq = b ^ 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int y = yw + r;
+                if (!(xin && y < ny)) continue;
+                const int row = 1 + wave * R + r;
+                const size_t i0 = (size_t)xl + sy * y + sz * q;
+                S lo[V], go[V];
+                bool anyin = false;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int col = 1 + lane * V + v;
+                    const C mxm = v > 0 ? m0[1][r][v - 1] : lM0[bq][row][col - 1];
+                    const C mxp = v < V - 1 ? m0[1][r][v + 1] : lM0[bq][row][col + 1];
+                    const C mym = r > 0 ? m0[1][r - 1][v] : lM0[bq][row - 1][col];
+                    const C myp = r < R - 1 ? m0[1][r + 1][v] : lM0[bq][row + 1][col];
+                    const C lm = lap7<DT>(m0[1][r][v], mxm, mxp, mym, myp, m0[0][r][v], mk[r][v], a);
+                    lo[v] = Tr::store(lkm[r][v] + lm, 0);
+                    go[v] = Tr::store(g1m[r][v], 0);
+                    if (inner(xl + v, y, q)) {
+                        anyin = true;
+                        const C txm = v > 0 ? tb[1][r][v - 1] : lTB[bq][row][col - 1];
+                        const C txp = v < V - 1 ? tb[1][r][v + 1] : lTB[bq][row][col + 1];
+                        const C tym = r > 0 ? tb[1][r - 1][v] : lTB[bq][row - 1][col];
+                        const C typ = r < R - 1 ? tb[1][r + 1][v] : lTB[bq][row + 1][col];
+                        const C ltk = lap7<DT>(tb[1][r][v], txm, txp, tym, typ, tb[0][r][v], tb[2][r][v], a);
+                        go[v] = Tr::store(g1m[r][v] + a.dtlam * lkm[r][v] * ltk, 0);
+                    }
+                }
+                vstore<S, V>(a.lout + i0, lo);
+                if (anyin) {
+                    if (xl >= 1 && xl + V - 1 <= nx - 2) {
+                        vstore<S, V>(a.gCi + i0, go);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v)
+                            if (xl + v >= 1 && xl + v <= nx - 2) a.gCi[i0 + v] = go[v];
+                    }
+                }
+            }
+        }
+
+        // shift the plane window
+        copy_rows(m1[0], m1[1]);
+        copy_rows(m1[1], m1[2]);
+        copy_rows(m1[2], m1[3]);
+        copy_rows(l1[0], l1[1]);
+        copy_rows(l1[1], l1[2]);
+        copy_rows(c1[0], c1[1]);
+        copy_rows(c1[1], c1[2]);
+        copy_rows(ta[0], ta[1]);
+        copy_rows(ta[1], ta[2]);
+        copy_rows(ta[2], ta[3]);
+        copy_rows(tb[0], tb[1]);
+        copy_rows(tb[1], tb[2]);
+        copy_rows(tb[2], tb[3]);
+        copy_rows(g[0], g[1]);
+        copy_rows(g1m, g1);
+        copy_rows(m0[0], m0[1]);
+        copy_rows(m0[1], mk);
+        copy_rows(lkm, lk);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            ym1[0][v] = ym1[1][v];
+            ym1[1][v] = ym1[2][v];
+            ym1[2][v] = ym1[3][v];
+            yl1[0][v] = yl1[1][v];
+            yl1[1][v] = yl1[2][v];
+            yc1[0][v] = yc1[1][v];
+            yc1[1][v] = yc1[2][v];
+            ym2[0][v] = ym2[1][v];
+        }
+        copy_vec(ytb[0], ytb[1]);
+        // yta: index 1 holds plane p+1's ring (staged this iteration); the
+        // ring of p+2 was loaded into index 0 and moves to index 1
+        copy_vec(yta[1], yta[0]);
+        xm1[0] = xm1[1];
+        xm1[1] = xm1[2];
+        xm1[2] = xm1[3];
+        xl1[0] = xl1[1];
+        xl1[1] = xl1[2];
+        xc1v[0] = xc1v[1];
+        xc1v[1] = xc1v[2];
+        xm2[0] = xm2[1];
+        xtb[0] = xtb[1];
+        xta[1] = xta[0];
+        b ^= 1;
+    }
+}
+
+}  // namespace diff3d

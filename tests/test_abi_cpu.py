@@ -179,3 +179,28 @@ def test_kernel_selection_roundtrip():
             d3.set_kernel(17)
     finally:
         d3.set_kernel(old)
+
+
+def test_default_tile_configurations_are_instantiated():
+    """Every default (and narrow fallback) tile configuration named in the
+    library source is one of its instantiated configurations."""
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from helpers import instantiated_configs
+    src = open(os.path.join(ROOT, "paper_2211_15634_amd", "csrc", "api.hip")).read()
+    sizes = {"F64": 8, "F32": 4, "BF16": 2, "BF16_RNE": 2}
+    kinds = {"FwdDefaults": "FWD", "Tb2Defaults": "TB2", "AdjDefaults": "ADJ", "Adj2Defaults": "ADJ2"}
+    found = 0
+    for struct, kind in kinds.items():
+        for dt, V, R, NW, NT in re.findall(r"struct %s<DIFF3D_(\w+)> \{ static constexpr ZKey wide\{(\d+), (\d+), (\d+), (\d+)\}"
+                                            % struct, src):
+            cfgs = instantiated_configs(kind, sizes[dt])
+            key = (int(V), int(R), int(NW), int(NT)) if kind in ("FWD", "TB2") else (int(V), int(R), int(NW))
+            assert key in cfgs, (struct, dt, key)
+            found += 1
+    assert found == 12
+    for name, kind in (("kNarrow", "FWD"), ("kNarrowTb2", "TB2"), ("kNarrowAdj2", "ADJ2")):
+        V, R, NW, NT = map(int, re.search(r"constexpr ZKey %s\{(\d+), (\d+), (\d+), (\d+)\}" % name, src).groups())
+        for size in ((8, 4, 2) if kind != "ADJ2" else (8, 4)):
+            key = (V, R, NW, NT) if kind != "ADJ2" else (V, R, NW)
+            assert key in instantiated_configs(kind, size), (name, size)

@@ -21,8 +21,8 @@ def _reset(lib):
     lib.set_kernel(lib.KERNEL_AUTO)
     yield
     lib.set_kernel(lib.KERNEL_AUTO)
-    os.environ.pop("DIFF3D_AZLEN", None)
-    os.environ.pop("DIFF3D_ACFG", None)
+    for k in ("DIFF3D_AZLEN", "DIFF3D_ACFG", "DIFF3D_BZLEN", "DIFF3D_BCFG"):
+        os.environ.pop(k, None)
 
 
 def _inputs(shape, seed=0):
@@ -88,6 +88,47 @@ def test_adjoint_configs(lib, dtype, cfg, azlen):
         rT0, rCi = _adjoint(lib, T0, Ci, g, s, 5, 3, dtype=tdt)
     np.testing.assert_array_equal(gT0, rT0)
     np.testing.assert_array_equal(gCi, rCi)
+
+
+def _adj2_cases():
+    out = []
+    for name, size in (("f64", 8), ("f32", 4)):
+        for cfg in instantiated_configs("ADJ2", size):
+            for zlen in (0, 1, 3):
+                out.append((name, cfg, zlen))
+    return out
+
+
+@pytest.mark.parametrize("dtype,cfg,zlen", _adj2_cases())
+def test_adjoint_two_step_configs(lib, dtype, cfg, zlen):
+    """Every instantiated two-step adjoint configuration and several z-chunk
+    lengths: FP64 bit-identical to the oracle, FP32 bit-identical to single
+    adjoint steps of the naive kernel."""
+    os.environ["DIFF3D_BZLEN"] = str(zlen)
+    os.environ["DIFF3D_BCFG"] = ",".join(str(c) for c in cfg)
+    lib.set_kernel(lib.KERNEL_AUTO)
+    T0, Ci, g, s = _inputs((13, 21, 128), seed=zlen + sum(cfg) + 7)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    gT0, gCi = _adjoint(lib, T0, Ci, g, s, 9, 4, dtype=tdt)
+    if dtype == "f64":
+        rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 9)
+    else:
+        lib.set_kernel(lib.KERNEL_NAIVE)
+        rT0, rCi = _adjoint(lib, T0, Ci, g, s, 9, 4, dtype=tdt)
+    np.testing.assert_array_equal(gT0, rT0)
+    np.testing.assert_array_equal(gCi, rCi)
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 3), (4, 5, 6), (5, 70, 33), (9, 3, 130), (6, 66, 64)])
+def test_adjoint_two_step_small_and_ragged(lib, shape):
+    os.environ["DIFF3D_BZLEN"] = "1"
+    lib.set_kernel(lib.KERNEL_AUTO)
+    T0, Ci, g, s = _inputs(shape, seed=11)
+    for nt, C in ((2, 2), (5, 3), (8, 8)):
+        rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
+        gT0, gCi = _adjoint(lib, T0, Ci, g, s, nt, C)
+        np.testing.assert_array_equal(gT0, rT0)
+        np.testing.assert_array_equal(gCi, rCi)
 
 
 def test_zero_steps(lib):
