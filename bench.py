@@ -338,10 +338,15 @@ def main():
         threads = oracle.max_threads()
         # a bounded sample: the oracle on the same 512^3 inputs, k steps, sized
         # from a one-step probe to about --cpu-seconds of work
+        # per-step time from two short runs (each also copies its two fields)
         t1 = time.perf_counter()
         oracle.forward(T0h, Cih, *sc, 1)
-        probe = time.perf_counter() - t1
-        k = max(1, min(nt, int(args.cpu_seconds / max(probe, 1e-3))))
+        t_one = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        oracle.forward(T0h, Cih, *sc, 3)
+        t_three = time.perf_counter() - t1
+        per_step = max((t_three - t_one) / 2, 1e-4)
+        k = max(1, min(10 * nt, int((args.cpu_seconds - (t_one - per_step)) / per_step)))
         t1 = time.perf_counter()
         oracle.forward(T0h, Cih, *sc, k)
         tc = time.perf_counter() - t1

@@ -1,0 +1,98 @@
+"""Reductions, loss seeds, the copy reference and extreme grid shapes."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from helpers import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 100003, 3 * 1024 * 256 + 5])
+def test_reductions(lib, dtype, n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(n)
+    xd, yd = torch.from_numpy(x).to("cuda", dtype), torch.from_numpy(y).to("cuda", dtype)
+    xq, yq = to_host(xd), to_host(yd)          # the values as stored
+    assert float(lib.field_max(xd)) == xq.max()
+    assert float(lib.norm2(xd)) == pytest.approx(float(np.sum(xq * xq)), rel=1e-13)
+    seed = torch.empty_like(xd)
+    L = float(lib.loss(xd.view(1, 1, n), yd.view(1, 1, n), seed.view(1, 1, n)))
+    r = xq - yq
+    assert L == pytest.approx(0.5 * float(np.sum(r * r)), rel=1e-13)
+    expect = torch.from_numpy(r).to("cuda", dtype)     # RNE of the FP64 difference
+    if dtype == torch.bfloat16:
+        # the library rounds the FP64 difference through FP32 to BF16 (nearest even)
+        expect = torch.from_numpy(r.astype(np.float32)).to("cuda").to(torch.bfloat16)
+    assert torch.equal(seed, expect)
+    # deterministic: the same bits on a second call
+    assert float(lib.norm2(xd)) == float(lib.norm2(xd))
+
+
+def test_unaligned_fields(lib):
+    """Fields that start 2 bytes past a 16-byte boundary (BF16 views): the
+    one-point-per-lane kernels and the 16-bit copy for the final swap."""
+    shape = (9, 20, 64)
+    n = int(np.prod(shape))
+    T0, Ci = workloads.bump(shape[2], shape[1], shape[0])
+    s = oracle.scalars(shape[2], shape[1], shape[0], Ci)
+    sc = (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+    outs = []
+    for off in (0, 1):
+        bufs = [torch.zeros(n + 8, dtype=torch.bfloat16, device="cuda") for _ in range(3)]
+        T, T2, C = (b[off:off + n].view(shape) for b in bufs)
+        T.copy_(to_dev(T0, torch.bfloat16))
+        C.copy_(to_dev(Ci, torch.bfloat16))
+        lib.set_sr_seed(3, 0)
+        lib.run(T, T2, C, *sc, 5)       # odd: ends with a copy T2 -> T
+        torch.cuda.synchronize()
+        outs.append(T.clone())
+    assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 2000), (3, 700, 3), (900, 3, 4), (5, 130, 257)])
+def test_extreme_shapes(lib, shape):
+    """Grids far from cubic: one tile row, one z-chunk, long z marches."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(sum(shape))
+    T0 = rng.random(shape)
+    Ci = 0.5 * (1.0 + 0.5 * rng.random(shape))
+    s = oracle.scalars(nx, ny, nz, Ci)
+    sc = (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+    ref = oracle.forward(T0, Ci, *sc, 7)
+    for kernel in (lib.KERNEL_NAIVE, lib.KERNEL_ZMARCH, lib.KERNEL_TB2):
+        lib.set_kernel(kernel)
+        T = to_dev(T0, torch.float64)
+        lib.run(T, torch.empty_like(T), to_dev(Ci, torch.float64), *sc, 7)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(to_host(T), ref)
+    lib.set_kernel(lib.KERNEL_AUTO)
+    g = rng.standard_normal(shape)
+    rT0, rCi = oracle.reverse(T0, Ci, g, *sc, 7)
+    T0d, Cid = to_dev(T0, torch.float64), to_dev(Ci, torch.float64)
+    ws = torch.empty(lib.adjoint_workspace_bytes(shape, 7, 3, torch.float64), dtype=torch.uint8, device="cuda")
+    gT0, gCi = torch.empty_like(T0d), torch.empty_like(T0d)
+    lib.adjoint_run(T0d, Cid, to_dev(g, torch.float64), gT0, gCi, ws, False, *sc, 7, 3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_host(gT0), rT0)
+    np.testing.assert_array_equal(to_host(gCi), rCi)
+
+
+def test_python_binding_rejects(lib):
+    T = torch.zeros((4, 5, 6), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        lib.step(T[:, :, :5], T, T, 1.0, 1e-3, 1.0, 1.0, 1.0)            # shape mismatch
+    with pytest.raises(ValueError):
+        lib.step(torch.zeros_like(T).transpose(0, 2), T, T, 1.0, 1e-3, 1.0, 1.0, 1.0)   # not contiguous
+    with pytest.raises(lib.Diff3dError):
+        lib.step(T, T, torch.zeros_like(T), 1.0, 1e-3, 1.0, 1.0, 1.0)     # T2 aliases T
+    with pytest.raises(TypeError):
+        lib.step(T.half(), T.half(), T.half(), 1.0, 1e-3, 1.0, 1.0, 1.0)
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        lib.run(T, torch.empty_like(T), T.clone(), 1.0, 1e-3, 1.0, 1.0, 1.0, 10, ckpt=ws, ckpt_every=3)
