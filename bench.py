@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "traffic_step_tb2_bump512_f64.json")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_step_tbs4_bump512_f64.json")
+PASS = 4                        # steps per launch of the FP64 time loop (S-step kernel)
 METRIC = "T_eff GB/s (% HBM peak) per 3-D diffusion step; adjoint/forward time ratio"
 
 
@@ -153,11 +154,14 @@ def main():
         s = d3.problem_scalars(Ci)
         T2 = T.clone()
         for _ in range(3):
+            d3.stepn(T2, T, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], PASS)
+        for _ in range(3):
             d3.step2(T2, T, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
         for _ in range(3):
             d3.step(T2, T, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
         torch.cuda.synchronize()
-        log("traffic probe done: 3 copies of 1 GiB, 3 two-step and 3 single-step launches on bump%d FP64" % n)
+        log("traffic probe done: 3 copies of 1 GiB, 3 %d-step, 3 two-step and 3 single-step launches on bump%d FP64"
+            % (PASS, n))
         return
     log("bench: generating bump%d inputs" % n)
     T0h, Cih = workloads.bump(n, n, n)
@@ -195,8 +199,9 @@ def main():
     log("bench: %.3f ms per run of %d steps, T_eff %.1f GB/s (wall %.3f s)" % (ms_per_step, nt, teff, wall))
 
     # ---------------------------------------------------------- kernel durations
-    # one launch between two events, on the stream it runs on: the two-step
-    # kernel (what the time loop runs for FP64) and the single-step kernel
+    # one launch between two events, on the stream it runs on: the S-step
+    # kernel (what the time loop runs for FP64), the two-step and the
+    # single-step kernels
     def kernel_ms(fn, reps=100, warm=30):
         # the clocks settle over the first tens of launches after an idle gap:
         # launch `warm` unrecorded ones first
@@ -213,9 +218,10 @@ def main():
         torch.cuda.synchronize()
         return sum(kev[2 * i].elapsed_time(kev[2 * i + 1]) for i in range(reps)) / reps
 
+    kS_ms = kernel_ms(lambda b, a: d3.stepn(b, a, Ci, *sc, PASS))
     k2_ms = kernel_ms(lambda b, a: d3.step2(b, a, Ci, *sc))
     k1_ms = kernel_ms(lambda b, a: d3.step(b, a, Ci, *sc))
-    achieved = 2 * bytes_step / (k2_ms / 1e3) / 1e9
+    achieved = PASS * bytes_step / (kS_ms / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -224,13 +230,16 @@ def main():
             traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "step_tb2 (two steps per launch)", "kernel_avg_us": round(k2_ms * 1e3, 2),
-                "algorithmic_bytes_per_launch": 2 * bytes_step,
-                "hbm_GBps": round(traffic / (k2_ms / 1e3) / 1e9, 1) if traffic else None}
+                "kernel": "step_tbs (%d steps per launch)" % PASS, "kernel_avg_us": round(kS_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": PASS * bytes_step,
+                "hbm_GBps": round(traffic / (kS_ms / 1e3) / 1e9, 1) if traffic else None}
     single = {"kernel": "step_zmarch (one step per launch)", "kernel_avg_us": round(k1_ms * 1e3, 2),
               "teff_GBps": round(bytes_step / (k1_ms / 1e3) / 1e9, 1)}
-    log("bench: two-step kernel %.1f us (%.1f GB/s algorithmic), single-step kernel %.1f us (%.1f GB/s)"
-        % (k2_ms * 1e3, achieved, k1_ms * 1e3, single["teff_GBps"]))
+    two = {"kernel": "step_tb2 (two steps per launch)", "kernel_avg_us": round(k2_ms * 1e3, 2),
+           "teff_GBps": round(2 * bytes_step / (k2_ms / 1e3) / 1e9, 1)}
+    log("bench: %d-step kernel %.1f us (%.1f GB/s algorithmic), two-step %.1f us (%.1f GB/s), single-step "
+        "kernel %.1f us (%.1f GB/s)" % (PASS, kS_ms * 1e3, achieved, k2_ms * 1e3, two["teff_GBps"], k1_ms * 1e3,
+                                        single["teff_GBps"]))
 
     # ---------------------------------------------------------- copy bandwidth
     del T2
@@ -372,7 +381,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "bump%d FP64: 3-D heat diffusion %d^3, nt=%d per step, Gaussian bump + 0.01 U[0,1] "
                                "noise, Ci=0.5(1+0.5u), lam=1, dt=min(dx^2)/lam/max(Ci)/6.1" % (n, n, nt),
-                   "nx": n, "ny": n, "nz": n, "nt": nt, "kernel": "two-step z-march (temporal blocking)",
+                   "nx": n, "ny": n, "nz": n, "nt": nt, "kernel": "four-step passes (temporal blocking over 4 steps)",
                    "parallelism": "single GPU"},
         "t_step_us": round(t_step * 1e6, 3),
         "teff_frac_hbm_peak": round(teff / HBM_PEAK_GBPS, 4),
@@ -381,6 +390,7 @@ def main():
         "run_ms_median": round(med, 4),
         "run_ms_ci95": [round(lo, 4), round(hi, 4)],
         "roofline": roofline,
+        "two_step": two,
         "single_step": single,
         "cpu_baseline": cpu,
     }

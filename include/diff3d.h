@@ -59,12 +59,18 @@ typedef enum {
 
 typedef enum {
     DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps, and in
-                                  diff3d_run two-step passes for FP64 and FP32 */
+                                  diff3d_run S-step passes for FP64 (S = 4) and FP32 (S = 3) */
     DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */
     DIFF3D_KERNEL_ZMARCH = 2,  /* x-y tiles marching along z, planes in registers and LDS */
-    DIFF3D_KERNEL_TB2 = 3      /* diff3d_run: two steps per pass (temporal blocking), z-march
+    DIFF3D_KERNEL_TB2 = 3,     /* diff3d_run: two steps per pass (temporal blocking), z-march
                                   for single steps; bit-identical results */
+    DIFF3D_KERNEL_TBS = 4      /* diff3d_run: S steps per pass with the S-step kernel (S from
+                                  diff3d_set_pass_steps), z-march for single steps; diff3d_stepn
+                                  also uses it for two steps; bit-identical results */
 } diff3d_kernel;
+
+/* Largest number of time steps one pass over memory can take (diff3d_stepn). */
+#define DIFF3D_MAX_PASS_STEPS 4
 
 /* Number of doubles in the device buffer `acc` of the reductions below. */
 #define DIFF3D_REDUCE_DOUBLES 1025
@@ -105,6 +111,20 @@ int diff3d_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz,
  * as diff3d_step: T2's boundary is not touched, T2 must not alias T or Ci. */
 int diff3d_step2(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
                  double dt, double rdx, double rdy, double rdz, int dtype, void* stream);
+
+/* nsteps time steps (1 <= nsteps <= DIFF3D_MAX_PASS_STEPS) in one pass over
+ * memory (temporal blocking over S = nsteps steps): each workgroup reads its
+ * tile of T padded by nsteps points on every side and computes the
+ * intermediate states on shrinking regions on chip.  Writes the interior of
+ * T2 with the state nsteps steps after T, bit-identical to nsteps diff3d_step
+ * calls through intermediate buffers (intermediates are rounded exactly as
+ * storing them would round them; stochastic rounding uses step indices
+ * s .. s+nsteps-1 and advances the index by nsteps).  nsteps = 1 is
+ * diff3d_step; nsteps = 2 runs the kernel of diff3d_step2 unless the selected
+ * kernel is DIFF3D_KERNEL_TBS.  Same buffer rules as diff3d_step; EINVAL for
+ * nsteps out of range. */
+int diff3d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
+                 double dt, double rdx, double rdy, double rdz, int nsteps, int dtype, void* stream);
 
 /* nt time steps with the buffer swap of Fig. 1.  First copies T's boundary
  * into T2, then alternates steps T -> T2 -> T ...  The result T_nt is always
@@ -163,6 +183,9 @@ int diff3d_copy(void* dst, const void* src, size_t bytes, void* stream);
 /* Select the forward step variant (diff3d_kernel); EINVAL if unknown. */
 int diff3d_set_kernel(int kernel);
 int diff3d_get_kernel(void);
+/* Steps per pass of diff3d_run under DIFF3D_KERNEL_TBS: 2 .. DIFF3D_MAX_PASS_STEPS,
+ * or 0 for the default of each dtype; EINVAL otherwise (1 is DIFF3D_KERNEL_ZMARCH). */
+int diff3d_set_pass_steps(int nsteps);
 /* Seed of the stochastic rounding of DIFF3D_BF16 and the step index the
  * next diff3d_step uses; diff3d_run uses indices step0 .. step0+nt-1 and
  * advances the index by nt, diff3d_step by 1. */

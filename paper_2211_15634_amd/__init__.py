@@ -31,7 +31,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 F64, F32, BF16, BF16_RNE = 0, 1, 2, 3
 OK, EINVAL, EDTYPE, EWORKSPACE, EHIP = 0, -1, -2, -3, -4
-KERNEL_AUTO, KERNEL_NAIVE, KERNEL_ZMARCH, KERNEL_TB2 = 0, 1, 2, 3
+KERNEL_AUTO, KERNEL_NAIVE, KERNEL_ZMARCH, KERNEL_TB2, KERNEL_TBS = 0, 1, 2, 3, 4
+MAX_PASS_STEPS = 4
 REDUCE_DOUBLES = 1025
 
 _vp, _i, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
@@ -46,6 +47,7 @@ _SIGS = {
     "diff3d_max": ([_vp, _sz, _i, _vp, _vp], _i),
     "diff3d_step": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _vp], _i),
     "diff3d_step2": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _vp], _i),
+    "diff3d_stepn": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _vp], _i),
     "diff3d_run": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _vp, _vp, _i], _i),
     "diff3d_adjoint_workspace_bytes": ([_i, _i, _i, _i, _i, _i], _sz),
     "diff3d_adjoint_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _i, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _i,
@@ -55,6 +57,7 @@ _SIGS = {
     "diff3d_copy": ([_vp, _vp, _sz, _vp], _i),
     "diff3d_set_kernel": ([_i], _i),
     "diff3d_get_kernel": ([], _i),
+    "diff3d_set_pass_steps": ([_i], _i),
     "diff3d_set_sr_seed": ([ctypes.c_uint64, ctypes.c_uint64], None),
     "diff3d_philox4x32_10": ([_u32p, _u32p, _u32p], None),
 }
@@ -75,6 +78,12 @@ class Diff3dError(RuntimeError):
 def _check(rc: int, where: str):
     if rc != OK:
         raise Diff3dError(rc, where)
+
+
+def _on(t: torch.Tensor):
+    """Make the tensor's device current for a library call (the kernels are
+    launched on the current device, into the tensor's current stream)."""
+    return torch.cuda.device(t.device)
 
 
 def _code(t: torch.Tensor, rounding: str = "sr") -> int:
@@ -121,6 +130,11 @@ def get_kernel() -> int:
     return _lib.diff3d_get_kernel()
 
 
+def set_pass_steps(nsteps: int) -> None:
+    """Steps per pass of run() under KERNEL_TBS (0 = the dtype's default)."""
+    _check(_lib.diff3d_set_pass_steps(int(nsteps)), "set_pass_steps")
+
+
 def set_sr_seed(seed: int, step0: int = 0) -> None:
     _lib.diff3d_set_sr_seed(seed & (2 ** 64 - 1), step0 & (2 ** 64 - 1))
 
@@ -153,7 +167,8 @@ def field_max(x: torch.Tensor) -> torch.Tensor:
     if not x.is_cuda or not x.is_contiguous():
         raise ValueError("x must be a contiguous GPU tensor")
     acc = _acc(x.device)
-    _check(_lib.diff3d_max(_p(x), x.numel(), _code(x), _p(acc), _stream(x)), "max")
+    with _on(x):
+        _check(_lib.diff3d_max(_p(x), x.numel(), _code(x), _p(acc), _stream(x)), "max")
     return acc[0]
 
 
@@ -172,8 +187,9 @@ def step(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: fl
     _field(T2, "T2", T)
     _field(Ci, "Ci", T)
     nz, ny, nx = T.shape
-    _check(_lib.diff3d_step(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _code(T, rounding),
-                            _stream(T)), "step")
+    with _on(T):
+        _check(_lib.diff3d_step(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _code(T, rounding),
+                                _stream(T)), "step")
 
 
 def step2(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
@@ -183,8 +199,21 @@ def step2(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: f
     _field(T2, "T2", T)
     _field(Ci, "Ci", T)
     nz, ny, nx = T.shape
-    _check(_lib.diff3d_step2(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _code(T, rounding),
-                             _stream(T)), "step2")
+    with _on(T):
+        _check(_lib.diff3d_step2(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _code(T, rounding),
+                                 _stream(T)), "step2")
+
+
+def stepn(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
+          rdz: float, nsteps: int, rounding: str = "sr") -> None:
+    """nsteps steps in one pass: interior of T2 = state nsteps steps after T."""
+    _field(T, "T")
+    _field(T2, "T2", T)
+    _field(Ci, "Ci", T)
+    nz, ny, nx = T.shape
+    with _on(T):
+        _check(_lib.diff3d_stepn(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nsteps),
+                                 _code(T, rounding), _stream(T)), "stepn")
 
 
 def run(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
@@ -205,8 +234,9 @@ def run(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: flo
         stride = (T.numel() * T.element_size() + 255) // 256 * 256
         if ckpt.numel() * ckpt.element_size() < max(nck - 1, 0) * stride:
             raise ValueError("ckpt buffer too small for %d checkpoints" % max(nck - 1, 0))
-    _check(_lib.diff3d_run(_p(T), _p(T2), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nt), _code(T, rounding),
-                           _stream(T), _p(ckpt), int(ckpt_every)), "run")
+    with _on(T):
+        _check(_lib.diff3d_run(_p(T), _p(T2), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nt), _code(T, rounding),
+                               _stream(T), _p(ckpt), int(ckpt_every)), "run")
 
 
 def adjoint_workspace_bytes(shape, nt: int, ckpt_every: int, dtype: torch.dtype) -> int:
@@ -222,10 +252,11 @@ def adjoint_run(T0, Ci, gTnt, gT0, gCi, workspace, ckpt_ready: bool, lam, dt, rd
     for name, t in (("Ci", Ci), ("gTnt", gTnt), ("gT0", gT0), ("gCi", gCi)):
         _field(t, name, T0)
     nz, ny, nx = T0.shape
-    _check(_lib.diff3d_adjoint_run(_p(T0), _p(Ci), _p(gTnt), _p(gT0), _p(gCi), _p(workspace),
-                                   workspace.numel() * workspace.element_size() if workspace is not None else 0,
-                                   int(bool(ckpt_ready)), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nt),
-                                   int(ckpt_every), _code(T0), _stream(T0)), "adjoint_run")
+    with _on(T0):
+        _check(_lib.diff3d_adjoint_run(_p(T0), _p(Ci), _p(gTnt), _p(gT0), _p(gCi), _p(workspace),
+                                       workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                       int(bool(ckpt_ready)), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nt),
+                                       int(ckpt_every), _code(T0), _stream(T0)), "adjoint_run")
 
 
 def loss(T: torch.Tensor, Tt: torch.Tensor, seed: torch.Tensor | None = None) -> torch.Tensor:
@@ -236,7 +267,8 @@ def loss(T: torch.Tensor, Tt: torch.Tensor, seed: torch.Tensor | None = None) ->
     if seed is not None:
         _field(seed, "seed", T)
     acc = _acc(T.device)
-    _check(_lib.diff3d_loss(_p(T), _p(Tt), _p(seed), T.numel(), _code(T), _p(acc), _stream(T)), "loss")
+    with _on(T):
+        _check(_lib.diff3d_loss(_p(T), _p(Tt), _p(seed), T.numel(), _code(T), _p(acc), _stream(T)), "loss")
     return acc[0]
 
 
@@ -245,7 +277,8 @@ def norm2(x: torch.Tensor) -> torch.Tensor:
     if not x.is_cuda or not x.is_contiguous():
         raise ValueError("x must be a contiguous GPU tensor")
     acc = _acc(x.device)
-    _check(_lib.diff3d_norm2(_p(x), x.numel(), _code(x), _p(acc), _stream(x)), "norm2")
+    with _on(x):
+        _check(_lib.diff3d_norm2(_p(x), x.numel(), _code(x), _p(acc), _stream(x)), "norm2")
     return acc[0]
 
 
@@ -254,7 +287,8 @@ def copy_(dst: torch.Tensor, src: torch.Tensor) -> None:
     nbytes = src.numel() * src.element_size()
     if dst.numel() * dst.element_size() < nbytes:
         raise ValueError("dst too small")
-    _check(_lib.diff3d_copy(_p(dst), _p(src), nbytes, _stream(src)), "copy")
+    with _on(src):
+        _check(_lib.diff3d_copy(_p(dst), _p(src), nbytes, _stream(src)), "copy")
 
 
 class Diffuse3D(torch.autograd.Function):

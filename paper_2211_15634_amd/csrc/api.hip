@@ -22,6 +22,7 @@ using namespace diff3d;
 namespace {
 
 int g_kernel = DIFF3D_KERNEL_AUTO;
+int g_pass_steps = 0;   // steps per pass of the S-step kernel in diff3d_run (0 = dtype default)
 uint64_t g_sr_seed = 0x5EEDu;
 uint64_t g_sr_step = 0;
 
@@ -301,6 +302,161 @@ int pair_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, in
     }
 }
 
+// S-step (temporal-blocked) configurations: S steps, W0 x H0 region per
+// workgroup (output tile (W0-2S) x (H0-2S)), NTH threads, NT non-temporal.
+struct SKey {
+    int S, W0, H0, NTH, NT;
+};
+
+inline bool skey_eq(const SKey& a, int S, int W0, int H0, int NTH, int NT)
+{
+    return a.S == S && a.W0 == W0 && a.H0 == H0 && a.NTH == NTH && a.NT == NT;
+}
+
+// Override "W0,H0,NTH[,NT]" for the S-step kernel from the environment
+// (tuning only; S is the pass length).
+inline bool env_skey(const char* name, SKey& k)
+{
+    const char* s = getenv(name);
+    if (!s || !*s) return false;
+    SKey r{k.S, 0, 0, 0, 1};
+    const int got = sscanf(s, "%d,%d,%d,%d", &r.W0, &r.H0, &r.NTH, &r.NT);
+    if (got < 3) return false;
+    k = r;
+    return true;
+}
+
+#define DIFF3D_TBS_CFGS_8(X) X(2, 64, 16, 512, 1) X(2, 64, 32, 512, 1) X(2, 64, 32, 1024, 1) X(3, 64, 24, 512, 1) \
+    X(3, 64, 32, 512, 1) X(3, 64, 32, 1024, 1) X(4, 64, 32, 512, 1) X(4, 64, 32, 1024, 1)
+#define DIFF3D_TBS_CFGS_4(X) X(2, 64, 32, 512, 1) X(2, 64, 64, 1024, 1) X(3, 64, 32, 512, 1) X(3, 64, 64, 1024, 1) \
+    X(3, 128, 32, 1024, 1) X(4, 64, 32, 512, 1) X(4, 64, 48, 768, 1)
+#define DIFF3D_TBS_CFGS_2(X) X(2, 64, 32, 512, 1) X(3, 64, 32, 512, 1) X(4, 64, 32, 512, 1)
+
+template <int DT>
+struct TbsDefaults;
+template <> struct TbsDefaults<DIFF3D_F64> {
+    static constexpr int S = 4;
+    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 1}, {3, 64, 32, 512, 1}, {4, 64, 32, 1024, 1}};
+};
+template <> struct TbsDefaults<DIFF3D_F32> {
+    static constexpr int S = 3;
+    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 64, 1024, 1}, {3, 128, 32, 1024, 1}, {4, 64, 48, 768, 1}};
+};
+template <> struct TbsDefaults<DIFF3D_BF16> {
+    static constexpr int S = 2;
+    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 1}, {3, 64, 32, 512, 1}, {4, 64, 32, 512, 1}};
+};
+template <> struct TbsDefaults<DIFF3D_BF16_RNE> {
+    static constexpr int S = 2;
+    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 1}, {3, 64, 32, 512, 1}, {4, 64, 32, 512, 1}};
+};
+
+// Workgroups of `kernel` (nth threads) resident at once on the current
+// device, from the occupancy calculator; cached per kernel and device.
+template <class F>
+long resident_slots(F kernel, int nth, int& cached_dev, long& cached)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev != cached_dev) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nth, 0) != hipSuccess) per_cu = 1;
+        cached = (long)max(cus, 1) * max(per_cu, 1);
+        cached_dev = dev;
+    }
+    return cached;
+}
+
+// z-chunking for kernels with few resident workgroups: equal-length blocks
+// run in rounds of `slots`, so pick the chunk count that minimises
+// rounds x (planes per chunk + `extra` halo planes), among counts that fill
+// the device (when the grid allows it).
+inline ZPlan plan_rounds(int nx, int ny, int nzout, int TX, int TY, int zlen_req, int extra, long slots)
+{
+    ZPlan p;
+    p.ntx = (nx + TX - 1) / TX;
+    p.nty = (ny + TY - 1) / TY;
+    const long tiles = (long)p.ntx * p.nty;
+    int zlen = zlen_req > 0 ? min(zlen_req, nzout) : nzout;
+    if (zlen_req <= 0) {
+        long best = -1;
+        const bool can_fill = tiles * nzout >= slots;
+        for (int nch = 1; nch <= nzout && nch <= 1024; ++nch) {
+            const int zl = (nzout + nch - 1) / nch;
+            const long blocks = tiles * ((nzout + zl - 1) / zl);
+            if (can_fill && blocks < slots) continue;
+            const long cost = ((blocks + slots - 1) / slots) * (long)(zl + extra);
+            if (best < 0 || cost < best) {
+                best = cost;
+                zlen = zl;
+            }
+        }
+    }
+    p.zlen = zlen;
+    p.nchunks = (nzout + zlen - 1) / zlen;
+    p.blocks = (unsigned)(tiles * p.nchunks);
+    return p;
+}
+
+template <int DT, int S, int W0, int H0, int NTH, int NT>
+int launch_tbs_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req)
+{
+    static int cdev = -1;
+    static long cslots = 0;
+    auto kernel = step_tbs<DT, S, W0, H0, NTH, NT != 0>;
+    const long slots = resident_slots(kernel, NTH, cdev, cslots);
+    const ZPlan p = plan_rounds(a.nx, a.ny, a.nz - 2, W0 - 2 * S, H0 - 2 * S, zlen_req, 2 * S, slots);
+    kernel<<<p.blocks, NTH, 0, st>>>(a, p.ntx, p.nty, p.zlen);
+    return hip_status();
+}
+
+// S steps T -> T2 in one pass (2 <= S <= DIFF3D_MAX_PASS_STEPS).
+template <int DT>
+int launch_tbs(const StepArgs<DT>& a, int nsteps, hipStream_t st)
+{
+    using Sz = typename Traits<DT>::S;
+    if (nsteps < 2 || nsteps > DIFF3D_MAX_PASS_STEPS) return DIFF3D_EINVAL;
+    SKey k = TbsDefaults<DT>::key[nsteps];
+    env_skey("DIFF3D_SCFG", k);
+    const int zlen = env_int("DIFF3D_SZLEN", 0);
+#define DIFF3D_TRY(s, w0, h0, nth, nt) \
+    if (skey_eq(k, s, w0, h0, nth, nt)) return launch_tbs_cfg<DT, s, w0, h0, nth, nt>(a, st, zlen);
+    if constexpr (sizeof(Sz) == 8) {
+        DIFF3D_TBS_CFGS_8(DIFF3D_TRY)
+    } else if constexpr (sizeof(Sz) == 4) {
+        DIFF3D_TBS_CFGS_4(DIFF3D_TRY)
+    } else {
+        DIFF3D_TBS_CFGS_2(DIFF3D_TRY)
+    }
+#undef DIFF3D_TRY
+    return DIFF3D_EINVAL;
+}
+
+template <int DT>
+int launch_multi(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
+                 double rdy, double rdz, int nsteps, uint64_t step_index, hipStream_t st)
+{
+    const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index);
+    return launch_tbs<DT>(a, nsteps, st);
+}
+
+int multi_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
+                   double rdx, double rdy, double rdz, int nsteps, uint64_t step_index, hipStream_t st)
+{
+    switch (dtype) {
+    case DIFF3D_F64:
+        return launch_multi<DIFF3D_F64>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, step_index, st);
+    case DIFF3D_F32:
+        return launch_multi<DIFF3D_F32>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, step_index, st);
+    case DIFF3D_BF16:
+        return launch_multi<DIFF3D_BF16>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, step_index, st);
+    case DIFF3D_BF16_RNE:
+        return launch_multi<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, step_index, st);
+    default: return DIFF3D_EDTYPE;
+    }
+}
+
 template <int DT>
 int launch_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
                 double rdy, double rdz, uint64_t step_index, hipStream_t st)
@@ -320,6 +476,43 @@ int step_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, in
     case DIFF3D_BF16_RNE:
         return launch_step<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
     default: return DIFF3D_EDTYPE;
+    }
+}
+
+// n steps in one pass: a single step, the two-step kernel, or the S-step
+// kernel (always for n >= 3; for n = 2 when it is the selected kernel).
+int pass_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
+                  double rdx, double rdy, double rdz, int n, uint64_t step_index, hipStream_t st)
+{
+    if (n == 1) return step_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    if (n == 2 && g_kernel != DIFF3D_KERNEL_TBS)
+        return pair_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    return multi_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, step_index, st);
+}
+
+int tbs_default_steps(int dtype)
+{
+    switch (dtype) {
+    case DIFF3D_F64: return TbsDefaults<DIFF3D_F64>::S;
+    case DIFF3D_F32: return TbsDefaults<DIFF3D_F32>::S;
+    case DIFF3D_BF16: return TbsDefaults<DIFF3D_BF16>::S;
+    default: return TbsDefaults<DIFF3D_BF16_RNE>::S;
+    }
+}
+
+// Steps per pass of diff3d_run for the selected kernel.  AUTO uses the
+// S-step kernel's measured best pass length for FP64 and FP32 (bound by HBM
+// bytes in single steps); the BF16 forms are bound by ALU work, which
+// temporal blocking does not reduce, so they keep single steps.  Shortened
+// passes of two steps go to the two-step kernel unless TBS is selected.
+int run_pass_steps(int dtype)
+{
+    switch (g_kernel) {
+    case DIFF3D_KERNEL_NAIVE:
+    case DIFF3D_KERNEL_ZMARCH: return 1;
+    case DIFF3D_KERNEL_TB2: return 2;
+    case DIFF3D_KERNEL_TBS: return g_pass_steps ? g_pass_steps : tbs_default_steps(dtype);
+    default: return (dtype == DIFF3D_F64 || dtype == DIFF3D_F32) ? tbs_default_steps(dtype) : 1;
     }
 }
 
@@ -394,19 +587,16 @@ int run_loop(int dtype, void* T, void* T2, const void* Ci, int nx, int ny, int n
     const size_t fbytes = npoints(nx, ny, nz) * elem_size(dtype);
     void* a = T;
     void* b = T2;
-    // AUTO pairs steps where the two-step pass is faster: FP64 and FP32 are
-    // bound by HBM bytes, the BF16 forms by ALU work (which pairing doubles
-    // per byte), so they keep single steps.
-    const bool pairs = g_kernel == DIFF3D_KERNEL_TB2 ||
-                       (g_kernel == DIFF3D_KERNEL_AUTO && (dtype == DIFF3D_F64 || dtype == DIFF3D_F32));
+    const int P = run_pass_steps(dtype);
     for (int it = 0; it < nt;) {
-        // two steps in one pass unless a checkpoint falls on the state in between
-        const bool mid_ckpt = ckpt && (it + 1) % C == 0 && it + 1 <= klast;
-        const int n = (pairs && nt - it >= 2 && !mid_ckpt) ? 2 : 1;
-        if (n == 2)
-            rc = pair_dispatch(dtype, b, a, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step + (uint64_t)it, st);
-        else
-            rc = step_dispatch(dtype, b, a, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step + (uint64_t)it, st);
+        // P steps in one pass, shortened at the end and where a checkpoint
+        // falls on a state inside the pass
+        int n = min(P, nt - it);
+        if (ckpt) {
+            const int next = (it / C + 1) * C;   // next checkpointed step
+            if (next <= klast && next - it < n) n = next - it;
+        }
+        rc = pass_dispatch(dtype, b, a, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, g_sr_step + (uint64_t)it, st);
         if (rc) return rc;
         void* s = a;
         a = b;
@@ -679,6 +869,20 @@ int diff3d_step2(void* T2, const void* T, const void* Ci, int nx, int ny, int nz
     return rc;
 }
 
+int diff3d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
+                 double rdy, double rdz, int nsteps, int dtype, void* stream)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (!T2 || !T || !Ci || check_grid(nx, ny, nz)) return DIFF3D_EINVAL;
+    if (nsteps < 1 || nsteps > DIFF3D_MAX_PASS_STEPS) return DIFF3D_EINVAL;
+    const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
+    if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb)) return DIFF3D_EINVAL;
+    const int rc =
+        pass_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, g_sr_step, as_stream(stream));
+    g_sr_step += (uint64_t)nsteps;
+    return rc;
+}
+
 int diff3d_run(void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
                double rdy, double rdz, int nt, int dtype, void* stream, void* ckpt, int ckpt_every)
 {
@@ -812,12 +1016,19 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
 
 int diff3d_set_kernel(int kernel)
 {
-    if (kernel < DIFF3D_KERNEL_AUTO || kernel > DIFF3D_KERNEL_TB2) return DIFF3D_EINVAL;
+    if (kernel < DIFF3D_KERNEL_AUTO || kernel > DIFF3D_KERNEL_TBS) return DIFF3D_EINVAL;
     g_kernel = kernel;
     return DIFF3D_OK;
 }
 
 int diff3d_get_kernel(void) { return g_kernel; }
+
+int diff3d_set_pass_steps(int nsteps)
+{
+    if (nsteps < 0 || nsteps == 1 || nsteps > DIFF3D_MAX_PASS_STEPS) return DIFF3D_EINVAL;
+    g_pass_steps = nsteps;
+    return DIFF3D_OK;
+}
 
 void diff3d_set_sr_seed(uint64_t seed, uint64_t step0)
 {

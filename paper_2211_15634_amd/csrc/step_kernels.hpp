@@ -39,6 +39,21 @@ __device__ inline typename Traits<DT>::C stencil_point(typename Traits<DT>::C t,
     return t + a.dt * ((a.lam * ci) * ((d2x * a.cx + d2y * a.cy) + d2z * a.cz));
 }
 
+// The same update with lam*Ci already formed (identical rounding).
+template <int DT>
+__device__ inline typename Traits<DT>::C stencil_point_lc(typename Traits<DT>::C t, typename Traits<DT>::C xm,
+                                                          typename Traits<DT>::C xp, typename Traits<DT>::C ym,
+                                                          typename Traits<DT>::C yp, typename Traits<DT>::C zm,
+                                                          typename Traits<DT>::C zp, typename Traits<DT>::C lamci,
+                                                          const StepArgs<DT>& a)
+{
+    using C = typename Traits<DT>::C;
+    const C d2x = (xp - t) - (t - xm);
+    const C d2y = (yp - t) - (t - ym);
+    const C d2z = (zp - t) - (t - zm);
+    return t + a.dt * (lamci * ((d2x * a.cx + d2y * a.cy) + d2z * a.cz));
+}
+
 // ------------------------------------------------------------------ naive
 // One thread per interior point; the seven reads of T go through the
 // caches.  Block 64 x 4 over (x, y); grid z strides over interior planes.

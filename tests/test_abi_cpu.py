@@ -124,6 +124,27 @@ def test_step2_validation():
     assert L.diff3d_step2(A, B, Cc, 64, 2, 64, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F64, None) == d3.EINVAL
 
 
+def test_stepn_validation():
+    L = d3._lib
+    args = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
+    for bad_n in (0, -1, d3.MAX_PASS_STEPS + 1):
+        assert L.diff3d_stepn(A, B, Cc, *args, bad_n, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_stepn(None, B, Cc, *args, 3, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_stepn(A, A, Cc, *args, 3, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_stepn(A, B, A, *args, 4, d3.F32, None) == d3.EINVAL
+    assert L.diff3d_stepn(A, B, Cc, *args, 3, 4, None) == d3.EDTYPE
+    assert L.diff3d_stepn(A, B, Cc, 64, 64, 2, 1.0, 1e-5, 1.0, 1.0, 1.0, 3, d3.F64, None) == d3.EINVAL
+
+
+def test_pass_steps_setting():
+    L = d3._lib
+    for bad in (-1, 1, d3.MAX_PASS_STEPS + 1):
+        assert L.diff3d_set_pass_steps(bad) == d3.EINVAL
+    for good in range(2, d3.MAX_PASS_STEPS + 1):
+        assert L.diff3d_set_pass_steps(good) == d3.OK
+    assert L.diff3d_set_pass_steps(0) == d3.OK
+
+
 def test_run_validation():
     L = d3._lib
     g = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
@@ -172,7 +193,7 @@ def test_reduction_and_copy_validation():
 def test_kernel_selection_roundtrip():
     old = d3.get_kernel()
     try:
-        for k in (d3.KERNEL_NAIVE, d3.KERNEL_ZMARCH, d3.KERNEL_AUTO):
+        for k in (d3.KERNEL_NAIVE, d3.KERNEL_ZMARCH, d3.KERNEL_TB2, d3.KERNEL_TBS, d3.KERNEL_AUTO):
             d3.set_kernel(k)
             assert d3.get_kernel() == k
         with pytest.raises(d3.Diff3dError):
@@ -204,3 +225,33 @@ def test_default_tile_configurations_are_instantiated():
         for size in ((8, 4, 2) if kind != "ADJ2" else (8, 4)):
             key = (V, R, NW, NT) if kind != "ADJ2" else (V, R, NW)
             assert key in instantiated_configs(kind, size), (name, size)
+
+
+def test_multi_step_configurations_fit_and_defaults_are_instantiated():
+    """Every S-step configuration fits the 160 KiB of LDS of a gfx950
+    workgroup and leaves an output tile; every per-dtype default (for each
+    pass length 2..4) is instantiated."""
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from helpers import instantiated_configs
+    src = open(os.path.join(ROOT, "paper_2211_15634_amd", "csrc", "api.hip")).read()
+    compute = {8: 8, 4: 4, 2: 4}          # LDS holds the arithmetic type
+    for size in (8, 4, 2):
+        cfgs = instantiated_configs("TBS", size)
+        assert cfgs
+        for S, W0, H0, NTH, NT in cfgs:
+            assert 2 <= S <= d3.MAX_PASS_STEPS
+            assert W0 - 2 * S > 0 and H0 - 2 * S > 0
+            assert NTH % 64 == 0 and NTH <= 1024
+            assert S * 2 * W0 * H0 * compute[size] <= 160 * 1024, (S, W0, H0)
+    sizes = {"F64": 8, "F32": 4, "BF16": 2, "BF16_RNE": 2}
+    found = 0
+    for dt, S, keys in re.findall(r"struct TbsDefaults<DIFF3D_(\w+)> \{\s*static constexpr int S = (\d+);\s*"
+                                  r"static constexpr SKey key\[5\] = \{(.*?)\};", src):
+        tup = [tuple(int(v) for v in t.split(",")) for t in re.findall(r"\{([\d ,]+)\}", keys)]
+        assert tup[:2] == [(0,), (0,)]
+        assert 2 <= int(S) <= d3.MAX_PASS_STEPS
+        for n, key in enumerate(tup[2:], start=2):
+            assert key[0] == n and key in instantiated_configs("TBS", sizes[dt]), (dt, key)
+            found += 1
+    assert found == 12
