@@ -326,29 +326,29 @@ inline bool env_skey(const char* name, SKey& k)
     return true;
 }
 
-#define DIFF3D_TBS_CFGS_8(X) X(2, 64, 16, 512, 1) X(2, 64, 32, 512, 1) X(2, 64, 32, 1024, 1) X(3, 64, 24, 512, 1) \
-    X(3, 64, 32, 512, 1) X(3, 64, 32, 1024, 1) X(4, 64, 32, 512, 1) X(4, 64, 32, 1024, 1)
-#define DIFF3D_TBS_CFGS_4(X) X(2, 64, 32, 512, 1) X(2, 64, 64, 1024, 1) X(3, 64, 32, 512, 1) X(3, 64, 64, 1024, 1) \
-    X(3, 128, 32, 1024, 1) X(4, 64, 32, 512, 1) X(4, 64, 48, 768, 1)
-#define DIFF3D_TBS_CFGS_2(X) X(2, 64, 32, 512, 1) X(3, 64, 32, 512, 1) X(4, 64, 32, 512, 1)
+#define DIFF3D_TBS_CFGS_8(X) X(2, 64, 16, 512, 1) X(2, 64, 32, 512, 0) X(3, 64, 32, 512, 0) X(3, 64, 32, 1024, 0) \
+    X(4, 64, 32, 512, 0) X(4, 64, 32, 1024, 0)
+#define DIFF3D_TBS_CFGS_4(X) X(2, 64, 32, 512, 1) X(2, 64, 64, 1024, 0) X(3, 64, 32, 512, 0) X(3, 128, 32, 1024, 0) \
+    X(4, 64, 32, 512, 0) X(4, 64, 48, 768, 0)
+#define DIFF3D_TBS_CFGS_2(X) X(2, 64, 32, 512, 1) X(3, 64, 32, 512, 0) X(4, 64, 32, 512, 0)
 
 template <int DT>
 struct TbsDefaults;
 template <> struct TbsDefaults<DIFF3D_F64> {
     static constexpr int S = 4;
-    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 1}, {3, 64, 32, 512, 1}, {4, 64, 32, 1024, 1}};
+    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 0}, {3, 64, 32, 512, 0}, {4, 64, 32, 1024, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_F32> {
     static constexpr int S = 3;
-    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 64, 1024, 1}, {3, 128, 32, 1024, 1}, {4, 64, 48, 768, 1}};
+    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 64, 1024, 0}, {3, 128, 32, 1024, 0}, {4, 64, 48, 768, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_BF16> {
     static constexpr int S = 2;
-    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 1}, {3, 64, 32, 512, 1}, {4, 64, 32, 512, 1}};
+    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 1}, {3, 64, 32, 512, 0}, {4, 64, 32, 512, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_BF16_RNE> {
     static constexpr int S = 2;
-    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 1}, {3, 64, 32, 512, 1}, {4, 64, 32, 512, 1}};
+    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 1}, {3, 64, 32, 512, 0}, {4, 64, 32, 512, 0}};
 };
 
 // Workgroups of `kernel` (nth threads) resident at once on the current
@@ -368,15 +368,19 @@ long resident_slots(F kernel, int nth, int& cached_dev, long& cached)
     return cached;
 }
 
+// Tiles along an axis of n points for regions of width w placed every t
+// points from the grid's edge, the last region reaching the far edge.
+inline int edge_tiles(int n, int w, int t) { return n <= w ? 1 : (n - w + t - 1) / t + 1; }
+
 // z-chunking for kernels with few resident workgroups: equal-length blocks
 // run in rounds of `slots`, so pick the chunk count that minimises
 // rounds x (planes per chunk + `extra` halo planes), among counts that fill
 // the device (when the grid allows it).
-inline ZPlan plan_rounds(int nx, int ny, int nzout, int TX, int TY, int zlen_req, int extra, long slots)
+inline ZPlan plan_rounds(int ntx, int nty, int nzout, int zlen_req, int extra, long slots)
 {
     ZPlan p;
-    p.ntx = (nx + TX - 1) / TX;
-    p.nty = (ny + TY - 1) / TY;
+    p.ntx = ntx;
+    p.nty = nty;
     const long tiles = (long)p.ntx * p.nty;
     int zlen = zlen_req > 0 ? min(zlen_req, nzout) : nzout;
     if (zlen_req <= 0) {
@@ -406,7 +410,8 @@ int launch_tbs_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req)
     static long cslots = 0;
     auto kernel = step_tbs<DT, S, W0, H0, NTH, NT != 0>;
     const long slots = resident_slots(kernel, NTH, cdev, cslots);
-    const ZPlan p = plan_rounds(a.nx, a.ny, a.nz - 2, W0 - 2 * S, H0 - 2 * S, zlen_req, 2 * S, slots);
+    const ZPlan p = plan_rounds(edge_tiles(a.nx, W0, W0 - 2 * S), edge_tiles(a.ny, H0, H0 - 2 * S), a.nz - 2,
+                                zlen_req, 2 * S, slots);
     kernel<<<p.blocks, NTH, 0, st>>>(a, p.ntx, p.nty, p.zlen);
     return hip_status();
 }

@@ -735,7 +735,11 @@ namespace diff3d {
 // region in x-y; its output tile is the region without a border of S points
 // (TX = W0 - 2S by TY = H0 - 2S).  Level s (s = 0 .. S, level 0 = the input
 // T^k) is computed on the region without a border of s points, so level S
-// is the tile.  With W0 = 64 each wave holds whole region rows (coalesced).  Every thread keeps
+// is the tile.  A region side that reaches the grid's boundary plane does
+// not shrink: the boundary values are the same at every level, so the
+// points next to it are computable at every level.  Regions therefore start
+// at the grid's edge (origin tx*TX, ty*TY) and the first and last tile of a
+// row or column output up to S-1 more points.  With W0 = 64 each wave holds whole region rows (coalesced).  Every thread keeps
 // the same region points at every level, so the z-history of a point (three
 // planes per level, four for the input with its prefetch) stays in that
 // thread's registers; x and y neighbours come from the level's plane staged
@@ -759,7 +763,11 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
     const int tx = (int)(t % (unsigned)ntx);
     const int rest = (int)(t / (unsigned)ntx);
     const int ty = rest % nty, tz = rest / nty;
-    const int x0 = tx * TX, y0 = ty * TY;
+    const int x0 = tx * TX, y0 = ty * TY;         // region origin
+    const bool ex0 = x0 == 0, ex1 = x0 + W0 >= nx, ey0 = y0 == 0, ey1 = y0 + H0 >= ny;
+    // output tile: [ox0, ox1) x [oy0, oy1)
+    const int ox0 = ex0 ? 1 : x0 + S, ox1 = ex1 ? nx - 1 : x0 + W0 - S;
+    const int oy0 = ey0 ? 1 : y0 + S, oy1 = ey1 ? ny - 1 : y0 + H0 - S;
     const int zb = 1 + tz * zlen;                 // output planes zb .. ze-1
     const int ze = min(nz - 1, zb + zlen);
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
@@ -777,17 +785,19 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
         live[k] = idx < A0;
         rr[k] = live[k] ? idx / W0 : 0;
         cc[k] = live[k] ? idx % W0 : 0;
-        gx[k] = x0 - S + cc[k];
-        gy[k] = y0 - S + rr[k];
+        gx[k] = x0 + cc[k];
+        gy[k] = y0 + rr[k];
         const int lx = min(max(gx[k], 0), nx - 1), ly = min(max(gy[k], 0), ny - 1);
         base[k] = (size_t)lx + sy * (size_t)ly;
-        const int cx = min(max(x0 - S + min(max(cc[k], 1), W0 - 2), 0), nx - 1);
-        const int cy = min(max(y0 - S + min(max(rr[k], 1), H0 - 2), 0), ny - 1);
+        const int cx = min(max(x0 + min(max(cc[k], 1), W0 - 2), 0), nx - 1);
+        const int cy = min(max(y0 + min(max(rr[k], 1), H0 - 2), 0), ny - 1);
         cbase[k] = (size_t)cx + sy * (size_t)cy;
     }
-    // point k belongs to the region of level s (border of s points removed)
+    // point k belongs to the region of level s (border of s points removed
+    // except on sides at the grid's boundary)
     auto in_level = [&](int k, int s) __attribute__((always_inline)) {
-        return live[k] && rr[k] >= s && rr[k] < H0 - s && cc[k] >= s && cc[k] < W0 - s;
+        return live[k] && (rr[k] >= s || ey0) && (rr[k] < H0 - s || ey1) && (cc[k] >= s || ex0) &&
+               (cc[k] < W0 - s || ex1);
     };
     auto interior_xy = [&](int k) __attribute__((always_inline)) {
         return gx[k] >= 1 && gx[k] <= nx - 2 && gy[k] >= 1 && gy[k] <= ny - 2;
@@ -894,7 +904,8 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
                     const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, ci[s][k], a);
                     if (s < S) {
                         v = Tr::load(Tr::store(w, rounding(gidx(k, z), s - 1)));
-                    } else if (z >= zb && z < ze) {
+                    } else if (z >= zb && z < ze && gx[k] >= ox0 && gx[k] < ox1 && gy[k] >= oy0 &&
+                               gy[k] < oy1) {
                         const S_ o = Tr::store(w, rounding(gidx(k, z), S - 1));
                         if (NT)
                             __builtin_nontemporal_store(o, a.T2 + gidx(k, z));

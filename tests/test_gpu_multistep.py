@@ -126,10 +126,12 @@ def test_stepn_equals_single_steps(lib, dtype, nsteps, kernel):
 
 
 @pytest.mark.parametrize("S", [2, 3, 4])
-@pytest.mark.parametrize("shape", [(3, 3, 3), (4, 5, 6), (5, 70, 33), (9, 3, 130), (20, 66, 64), (6, 130, 7)])
+@pytest.mark.parametrize("shape", [(3, 3, 3), (4, 5, 6), (5, 70, 33), (9, 3, 130), (20, 66, 64), (6, 130, 7),
+                                   (7, 65, 65), (9, 120, 121), (5, 33, 200), (6, 57, 177)])
 def test_tbs_small_and_ragged(lib, S, shape):
     """S-step passes on grids with one or two interior planes, regions
-    wider than the grid, ragged x and y tiles and one-plane z-chunks."""
+    wider than the grid, a last region ending exactly on or one point past
+    the grid's edge, ragged x and y tiles and one-plane z-chunks."""
     os.environ["DIFF3D_SZLEN"] = "1"
     lib.set_kernel(lib.KERNEL_TBS)
     lib.set_pass_steps(S)
