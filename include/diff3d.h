@@ -58,15 +58,19 @@ typedef enum {
 } diff3d_status;
 
 typedef enum {
-    DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps, and in
-                                  diff3d_run S-step passes for FP64 (S = 4) and FP32 (S = 3) */
+    DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps; in
+                                  diff3d_run S-step passes for FP64 (S = 4) and FP32 (S = 3); in
+                                  diff3d_adjoint_run fused three-step reverse passes for FP64 and
+                                  two-step passes over recomputed states for FP32 */
     DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */
     DIFF3D_KERNEL_ZMARCH = 2,  /* x-y tiles marching along z, planes in registers and LDS */
     DIFF3D_KERNEL_TB2 = 3,     /* diff3d_run: two steps per pass (temporal blocking), z-march
                                   for single steps; bit-identical results */
     DIFF3D_KERNEL_TBS = 4      /* diff3d_run: S steps per pass with the S-step kernel (S from
                                   diff3d_set_pass_steps), z-march for single steps; diff3d_stepn
-                                  also uses it for two steps; bit-identical results */
+                                  also uses it for two steps; diff3d_adjoint_run: fused reverse
+                                  passes of min(S, 3) steps (forward states recomputed on chip);
+                                  bit-identical results */
 } diff3d_kernel;
 
 /* Largest number of time steps one pass over memory can take (diff3d_stepn). */
@@ -152,8 +156,11 @@ size_t diff3d_adjoint_workspace_bytes(int nx, int ny, int nz, int nt, int ckpt_e
  *   mu   = dt*lam*Ci*lambda_{k+1} on interior points, 0 elsewhere
  *   lambda_k = lambda_{k+1} + Lap(mu)          at every point (mu = 0 outside)
  * Lap is the weighted 7-point expression of the step.  States T_k are
- * recomputed segment by segment from checkpoints every ckpt_every steps
- * (computed here from T0 unless ckpt_ready = 1, in which case the workspace
+ * recomputed segment by segment from checkpoints every ckpt_every steps:
+ * either every state of the segment (then one or two reverse steps per
+ * launch), or only the states at the starts of fused reverse passes, which
+ * recompute the states in between on chip (diff3d_kernel).  Checkpoints are
+ * computed here from T0 unless ckpt_ready = 1, in which case the workspace
  * already holds them from diff3d_run with the same T0, Ci, scalars, nt,
  * ckpt_every and dtype).  Only DIFF3D_F64 and DIFF3D_F32 are supported
  * (EDTYPE otherwise).  gT0, gCi and the workspace must not overlap each

@@ -13,6 +13,7 @@
 #include "adjoint_kernels.hpp"
 #include "common.hpp"
 #include "diff3d.h"
+#include "rev_kernels.hpp"
 #include "step_kernels.hpp"
 #include "tb_kernels.hpp"
 #include "util_kernels.hpp"
@@ -744,6 +745,108 @@ int adj2_dispatch(int dtype, void* lout, const void* lin, const void* Ci, const 
     }
 }
 
+// Fused reverse passes (forward states recomputed on chip): W0 x H0 region,
+// NTH threads, per number of steps S.
+struct RKey {
+    int W0, H0, NTH;
+};
+
+#define DIFF3D_REV_CFGS_8(X) X(2, 64, 16, 1024) X(3, 64, 16, 1024) X(3, 64, 16, 512)
+#define DIFF3D_REV_CFGS_4(X) X(2, 64, 32, 1024) X(3, 64, 32, 1024) X(3, 64, 16, 1024)
+constexpr int kMaxRevSteps = 3;
+
+// Measured at 256^3 (nt = 200, C = 14): FP64 three-step passes on 64 x 16
+// regions take the reverse sweep from 40.3 ms (two-step kernels) to 33-34 ms;
+// for FP32 the fused passes are no faster than the two-step kernels (21.8 vs
+// 21.5 ms), so AUTO keeps those there.
+template <int DT>
+struct RevDefaults;
+template <> struct RevDefaults<DIFF3D_F64> {
+    static constexpr int S = 3;
+    static constexpr RKey key[kMaxRevSteps + 1] = {{0, 0, 0}, {0, 0, 0}, {64, 16, 1024}, {64, 16, 1024}};
+};
+template <> struct RevDefaults<DIFF3D_F32> {
+    static constexpr int S = 2;
+    static constexpr RKey key[kMaxRevSteps + 1] = {{0, 0, 0}, {0, 0, 0}, {64, 32, 1024}, {64, 32, 1024}};
+};
+
+template <int DT, int S, int W0, int H0, int NTH>
+int launch_rev_cfg(const RevArgs<DT>& a, hipStream_t st, int zlen_req)
+{
+    static int cdev = -1;
+    static long cslots = 0;
+    auto kernel = rev_tbs<DT, S, W0, H0, NTH>;
+    const long slots = resident_slots(kernel, NTH, cdev, cslots);
+    const ZPlan p = plan_rounds(edge_tiles(a.nx, W0, W0 - 2 * S), edge_tiles(a.ny, H0, H0 - 2 * S), a.nz, zlen_req,
+                                3 * S - 3, slots);
+    kernel<<<p.blocks, NTH, 0, st>>>(a, p.ntx, p.nty, p.zlen);
+    return hip_status();
+}
+
+// S reverse steps lambda_{k+S} -> lambda_k from the state T_k (2 <= S <= kMaxRevSteps).
+template <int DT>
+int launch_rev(int nsteps, void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny,
+               int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+{
+    using Sz = typename Traits<DT>::S;
+    using C = typename Traits<DT>::C;
+    if (nsteps < 2 || nsteps > kMaxRevSteps) return DIFF3D_EINVAL;
+    RevArgs<DT> a;
+    a.lout = static_cast<Sz*>(lout);
+    a.lin = static_cast<const Sz*>(lin);
+    a.Ci = static_cast<const Sz*>(Ci);
+    a.Tk = static_cast<const Sz*>(Tk);
+    a.gCi = static_cast<Sz*>(gCi);
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.lam = (C)lam;
+    a.dt = (C)dt;
+    a.dtlam = (C)dt * (C)lam;
+    a.cx = (C)(rdx * rdx);
+    a.cy = (C)(rdy * rdy);
+    a.cz = (C)(rdz * rdz);
+    RKey k = RevDefaults<DT>::key[nsteps];
+    {
+        // tuning override "S,W0,H0,NTH" for passes of S steps
+        const char* e = getenv("DIFF3D_RCFG");
+        int es = 0;
+        RKey r{0, 0, 0};
+        if (e && *e && sscanf(e, "%d,%d,%d,%d", &es, &r.W0, &r.H0, &r.NTH) == 4 && es == nsteps) k = r;
+    }
+    const int zlen = env_int("DIFF3D_RZLEN", 0);
+#define DIFF3D_TRY(s, w0, h0, nth) \
+    if (nsteps == s && k.W0 == w0 && k.H0 == h0 && k.NTH == nth) return launch_rev_cfg<DT, s, w0, h0, nth>(a, st, zlen);
+    if constexpr (sizeof(Sz) == 8) {
+        DIFF3D_REV_CFGS_8(DIFF3D_TRY)
+    } else {
+        DIFF3D_REV_CFGS_4(DIFF3D_TRY)
+    }
+#undef DIFF3D_TRY
+    return DIFF3D_EINVAL;
+}
+
+int rev_dispatch(int dtype, int nsteps, void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx,
+                 int ny, int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+{
+    switch (dtype) {
+    case DIFF3D_F64:
+        return launch_rev<DIFF3D_F64>(nsteps, lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    case DIFF3D_F32:
+        return launch_rev<DIFF3D_F32>(nsteps, lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    default: return DIFF3D_EDTYPE;
+    }
+}
+
+// Steps per fused reverse pass: the dtype's default, or the S-step pass
+// length when set (capped at kMaxRevSteps).
+int rev_pass_steps(int dtype)
+{
+    const int d = dtype == DIFF3D_F64 ? RevDefaults<DIFF3D_F64>::S : RevDefaults<DIFF3D_F32>::S;
+    if (g_kernel == DIFF3D_KERNEL_TBS && g_pass_steps >= 2) return min(g_pass_steps, kMaxRevSteps);
+    return d;
+}
+
 int adj_dispatch(int dtype, void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny,
                  int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
 {
@@ -966,6 +1069,46 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
     for (int i = 0; i < segn; ++i) {
         rc = boundary_dispatch(dtype, seg(i), T0, nx, ny, nz, st);
         if (rc) return rc;
+    }
+
+    if (g_kernel == DIFF3D_KERNEL_TBS || (g_kernel == DIFF3D_KERNEL_AUTO && dtype == DIFF3D_F64)) {
+        // Fused reverse passes of P steps (the first pass of a segment takes
+        // the remainder): only the states at pass starts are recomputed (by
+        // forward passes of the same lengths), the pass recomputes the rest
+        // on chip.  lambda alternates between gT0 and W so that the last
+        // launch writes gT0.
+        const int P = rev_pass_steps(dtype);
+        auto npass = [&](int len) { return (len + P - 1) / P; };
+        long nlaunch = 0;
+        for (int j = nck - 1; j >= 0; --j) nlaunch += npass(((j * C + C < nt) ? j * C + C : nt) - j * C);
+        long launch = 0;
+        const void* lin = gTnt;
+        for (int j = nck - 1; j >= 0; --j) {
+            const int s = j * C;
+            const int len = ((s + C < nt) ? s + C : nt) - s;
+            const int m = npass(len);
+            const int r = len - (m - 1) * P;      // first pass: 1 .. P steps
+            const void* base = j == 0 ? T0 : slot(j);
+            // states at the starts of passes 1 .. m-1 into seg(0) .. seg(m-2)
+            const void* src = base;
+            for (int i = 1; i < m; ++i) {
+                rc = pass_dispatch(dtype, seg(i - 1), src, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, i == 1 ? r : P, 0,
+                                   st);
+                if (rc) return rc;
+                src = seg(i - 1);
+            }
+            for (int i = m - 1; i >= 0; --i) {
+                const int n = i == 0 ? r : P;
+                const void* Tk = i == 0 ? base : seg(i - 1);
+                void* out = ((nlaunch - 1 - launch) % 2 == 0) ? gT0 : W;
+                rc = n >= 2 ? rev_dispatch(dtype, n, out, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st)
+                            : adj_dispatch(dtype, out, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+                if (rc) return rc;
+                lin = out;
+                ++launch;
+            }
+        }
+        return DIFF3D_OK;
     }
 
     // adjoint launches (two steps per launch inside a segment where enabled);

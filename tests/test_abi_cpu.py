@@ -255,3 +255,29 @@ def test_multi_step_configurations_fit_and_defaults_are_instantiated():
             assert key[0] == n and key in instantiated_configs("TBS", sizes[dt]), (dt, key)
             found += 1
     assert found == 12
+
+
+def test_fused_reverse_configurations_fit_and_defaults_are_instantiated():
+    """Every fused reverse-pass configuration fits the 160 KiB of LDS of a
+    gfx950 workgroup (two staged fields per level) and leaves a tile; every
+    per-dtype default is instantiated."""
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from helpers import instantiated_configs
+    src = open(os.path.join(ROOT, "paper_2211_15634_amd", "csrc", "api.hip")).read()
+    for size in (8, 4):
+        cfgs = instantiated_configs("REV", size)
+        assert cfgs
+        for S, W0, H0, NTH in cfgs:
+            assert W0 - 2 * S > 0 and H0 - 2 * S > 0 and W0 % 64 == 0 and NTH % 64 == 0 and NTH <= 1024
+            assert 2 * S * 2 * W0 * H0 * size <= 160 * 1024, (S, W0, H0)
+    found = 0
+    for dt, S, keys in re.findall(r"struct RevDefaults<DIFF3D_(\w+)> \{\s*static constexpr int S = (\d+);\s*"
+                                  r"static constexpr RKey key\[kMaxRevSteps \+ 1\] = \{(.*?)\};", src):
+        tup = [tuple(int(v) for v in t.split(",")) for t in re.findall(r"\{([\d ,]+)\}", keys)]
+        size = {"F64": 8, "F32": 4}[dt]
+        for n, key in enumerate(tup[2:], start=2):
+            assert (n,) + key in instantiated_configs("REV", size), (dt, n, key)
+            found += 1
+        assert 2 <= int(S) <= len(tup) - 1
+    assert found == 4

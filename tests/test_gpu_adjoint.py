@@ -51,9 +51,10 @@ def _adjoint(lib, T0, Ci, g, s, nt, C, dtype=torch.float64, ready=False):
 
 @pytest.mark.parametrize("shape,nt,C", [((6, 5, 7), 5, 2), ((19, 37, 131), 9, 4), ((21, 20, 128), 13, 5),
                                         ((3, 3, 3), 4, 3), ((8, 70, 64), 7, 1), ((9, 9, 192), 6, 10)])
-@pytest.mark.parametrize("kernel", ["naive", "zmarch", "auto"])
+@pytest.mark.parametrize("kernel", ["naive", "zmarch", "tb2", "auto"])
 def test_fp64_matches_oracle_bitwise(lib, shape, nt, C, kernel):
-    lib.set_kernel({"naive": lib.KERNEL_NAIVE, "zmarch": lib.KERNEL_ZMARCH, "auto": lib.KERNEL_AUTO}[kernel])
+    lib.set_kernel({"naive": lib.KERNEL_NAIVE, "zmarch": lib.KERNEL_ZMARCH, "tb2": lib.KERNEL_TB2,
+                    "auto": lib.KERNEL_AUTO}[kernel])
     T0, Ci, g, s = _inputs(shape)
     rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
     for ready in (False, True):
@@ -106,7 +107,7 @@ def test_adjoint_two_step_configs(lib, dtype, cfg, zlen):
     adjoint steps of the naive kernel."""
     os.environ["DIFF3D_BZLEN"] = str(zlen)
     os.environ["DIFF3D_BCFG"] = ",".join(str(c) for c in cfg)
-    lib.set_kernel(lib.KERNEL_AUTO)
+    lib.set_kernel(lib.KERNEL_TB2)
     T0, Ci, g, s = _inputs((13, 21, 128), seed=zlen + sum(cfg) + 7)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     gT0, gCi = _adjoint(lib, T0, Ci, g, s, 9, 4, dtype=tdt)
@@ -122,7 +123,7 @@ def test_adjoint_two_step_configs(lib, dtype, cfg, zlen):
 @pytest.mark.parametrize("shape", [(3, 3, 3), (4, 5, 6), (5, 70, 33), (9, 3, 130), (6, 66, 64)])
 def test_adjoint_two_step_small_and_ragged(lib, shape):
     os.environ["DIFF3D_BZLEN"] = "1"
-    lib.set_kernel(lib.KERNEL_AUTO)
+    lib.set_kernel(lib.KERNEL_TB2)
     T0, Ci, g, s = _inputs(shape, seed=11)
     for nt, C in ((2, 2), (5, 3), (8, 8)):
         rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
