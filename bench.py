@@ -91,6 +91,15 @@ def large_form(d3, workloads, torch, np, dev, stream, n=1024, nt=500, C=32):
     torch.cuda.synchronize()
     tf = ev[0].elapsed_time(ev[1]) / 1e3
     tb = ev[2].elapsed_time(ev[3]) / 1e3
+    # the same forward in single-step launches (the paper's step)
+    d3.set_kernel(d3.KERNEL_ZMARCH)
+    T.copy_(T0)
+    ev[0].record(stream)
+    d3.run(T, T2, Ci, *sc, nt, ckpt=ws, ckpt_every=C)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    d3.set_kernel(d3.KERNEL_AUTO)
+    tf1 = ev[0].elapsed_time(ev[1]) / 1e3
     nck = (nt + C - 1) // C
     recompute = nt - nck
     gnorm = float(d3.norm2(gT0)) ** 0.5
@@ -98,6 +107,7 @@ def large_form(d3, workloads, torch, np, dev, stream, n=1024, nt=500, C=32):
     out = {"large_workload": "1024^3 FP32, nt=%d, checkpoint every %d (%d checkpoints), workspace %.1f GB"
                              % (nt, C, nck, ws_bytes / 1e9),
            "large_fwd_s": round(tf, 4), "large_bwd_s": round(tb, 4), "large_ratio": round(tb / tf, 3),
+           "large_fwd_single_step_s": round(tf1, 4), "large_ratio_vs_single_step": round(tb / tf1, 3),
            "large_teff_fwd_GBps": round(3 * esz * N * nt / tf / 1e9, 1),
            "large_teff_bwd_GBps": round((3 * recompute + 6 * nt) * esz * N / tb / 1e9, 1),
            "large_loss": float(loss), "large_gradnorm_T0": gnorm, "large_finite": finite}
@@ -119,8 +129,8 @@ def main():
     ap.add_argument("--large", action="store_true",
                     help="also run the 1024^3 FP32 forward + checkpointed adjoint form (nt=500, C=32, ~240 GB)")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="only launch a 1 GiB copy, the two-step and the single-step kernel, 3 times each "
-                         "(for counter runs)")
+                    help="only launch a 1 GiB copy, the four-step, two-step and single-step kernels, 3 times "
+                         "each (for counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -60,8 +60,9 @@ typedef enum {
 typedef enum {
     DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps; in
                                   diff3d_run S-step passes for FP64 (S = 4) and FP32 (S = 3); in
-                                  diff3d_adjoint_run fused three-step reverse passes for FP64 and
-                                  two-step passes over recomputed states for FP32 */
+                                  diff3d_adjoint_run fused three-step reverse passes (FP32 fields
+                                  within the 256 MB last-level cache: two-step passes over
+                                  recomputed states) */
     DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */
     DIFF3D_KERNEL_ZMARCH = 2,  /* x-y tiles marching along z, planes in registers and LDS */
     DIFF3D_KERNEL_TB2 = 3,     /* diff3d_run: two steps per pass (temporal blocking), z-march

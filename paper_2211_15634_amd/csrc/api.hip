@@ -755,10 +755,13 @@ struct RKey {
 #define DIFF3D_REV_CFGS_4(X) X(2, 64, 32, 1024) X(3, 64, 32, 1024) X(3, 64, 16, 1024)
 constexpr int kMaxRevSteps = 3;
 
-// Measured at 256^3 (nt = 200, C = 14): FP64 three-step passes on 64 x 16
-// regions take the reverse sweep from 40.3 ms (two-step kernels) to 33-34 ms;
-// for FP32 the fused passes are no faster than the two-step kernels (21.8 vs
-// 21.5 ms), so AUTO keeps those there.
+// Measured: FP64 three-step passes on 64 x 16 regions take the 256^3 reverse
+// sweep (nt = 200, C = 14) from 40.3 ms (two-step kernels over recomputed
+// states) to 33 ms; FP32 three-step passes take the 1024^3 one (nt = 500,
+// C = 32) from 3.26 to 2.74 s.  With FP32 fields inside the last-level cache
+// (256^3: 67 MB) re-reading recomputed states is cheap and the two-step
+// kernels are as fast (21.5 vs 21.8 ms), so AUTO keeps them there.
+constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
 template <int DT>
 struct RevDefaults;
 template <> struct RevDefaults<DIFF3D_F64> {
@@ -766,7 +769,7 @@ template <> struct RevDefaults<DIFF3D_F64> {
     static constexpr RKey key[kMaxRevSteps + 1] = {{0, 0, 0}, {0, 0, 0}, {64, 16, 1024}, {64, 16, 1024}};
 };
 template <> struct RevDefaults<DIFF3D_F32> {
-    static constexpr int S = 2;
+    static constexpr int S = 3;
     static constexpr RKey key[kMaxRevSteps + 1] = {{0, 0, 0}, {0, 0, 0}, {64, 32, 1024}, {64, 32, 1024}};
 };
 
@@ -1071,7 +1074,8 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
         if (rc) return rc;
     }
 
-    if (g_kernel == DIFF3D_KERNEL_TBS || (g_kernel == DIFF3D_KERNEL_AUTO && dtype == DIFF3D_F64)) {
+    if (g_kernel == DIFF3D_KERNEL_TBS ||
+        (g_kernel == DIFF3D_KERNEL_AUTO && (dtype == DIFF3D_F64 || fb > kLastLevelCacheBytes))) {
         // Fused reverse passes of P steps (the first pass of a segment takes
         // the remainder): only the states at pass starts are recomputed (by
         // forward passes of the same lengths), the pass recomputes the rest
