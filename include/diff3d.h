@@ -59,8 +59,9 @@ typedef enum {
 
 typedef enum {
     DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps; in
-                                  diff3d_run S-step passes for FP64 (S = 4), FP32 (S = 3) and
-                                  BF16 with round-to-nearest (S = 2); in
+                                  diff3d_run S-step passes for FP64 (S = 4), FP32 (S = 3), BF16
+                                  with stochastic rounding (S = 3) and BF16 with
+                                  round-to-nearest (S = 2); in
                                   diff3d_adjoint_run fused three-step reverse passes (FP32 fields
                                   within the 256 MB last-level cache: two-step passes over
                                   recomputed states) */
@@ -127,7 +128,7 @@ int diff3d_step2(void* T2, const void* T, const void* Ci, int nx, int ny, int nz
  * storing them would round them; stochastic rounding uses step indices
  * s .. s+nsteps-1 and advances the index by nsteps).  nsteps = 1 is
  * diff3d_step; nsteps = 2 runs the kernel of diff3d_step2 except under
- * DIFF3D_KERNEL_TBS (and, under DIFF3D_KERNEL_AUTO, for DIFF3D_BF16_RNE).  Same buffer rules as diff3d_step; EINVAL for
+ * DIFF3D_KERNEL_TBS (and, under DIFF3D_KERNEL_AUTO, for the BF16 forms).  Same buffer rules as diff3d_step; EINVAL for
  * nsteps out of range. */
 int diff3d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
                  double dt, double rdx, double rdy, double rdz, int nsteps, int dtype, void* stream);

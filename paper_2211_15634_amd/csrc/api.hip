@@ -344,7 +344,7 @@ template <> struct TbsDefaults<DIFF3D_F32> {
     static constexpr SKey key[5] = {{0}, {0}, {2, 64, 64, 1024, 0}, {3, 128, 32, 1024, 0}, {4, 64, 48, 768, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_BF16> {
-    static constexpr int S = 2;
+    static constexpr int S = 3;
     static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 1024, 0}, {3, 64, 32, 1024, 0}, {4, 64, 32, 1024, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_BF16_RNE> {
@@ -487,13 +487,15 @@ int step_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, in
 
 // n steps in one pass: a single step, the two-step kernel, or the S-step
 // kernel (always for n >= 3; for n = 2 when it is selected, and under AUTO
-// for BF16 with round-to-nearest, where it is faster: 140 vs 340 us per step
-// at 512^3; for FP64 and FP32 the two-step kernel is faster).
+// for the BF16 forms, where it is faster: 140 vs 340 us per step at 512^3
+// with round-to-nearest, 305 vs 584 with stochastic rounding; for FP64 and
+// FP32 the two-step kernel is faster).
 int pass_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
                   double rdx, double rdy, double rdz, int n, uint64_t step_index, hipStream_t st)
 {
     if (n == 1) return step_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
-    const bool tbs2 = g_kernel == DIFF3D_KERNEL_TBS || (g_kernel == DIFF3D_KERNEL_AUTO && dtype == DIFF3D_BF16_RNE);
+    const bool tbs2 = g_kernel == DIFF3D_KERNEL_TBS ||
+                      (g_kernel == DIFF3D_KERNEL_AUTO && (dtype == DIFF3D_BF16 || dtype == DIFF3D_BF16_RNE));
     if (n == 2 && !tbs2)
         return pair_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
     return multi_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, step_index, st);
@@ -512,9 +514,8 @@ int tbs_default_steps(int dtype)
 // Steps per pass of diff3d_run for the selected kernel.  AUTO uses the
 // S-step kernel's measured best pass length: 4 for FP64, 3 for FP32, 2 for
 // BF16 with round-to-nearest (bound by ALU work more than bytes: 140 us per
-// step against 207 for single steps at 512^3); BF16 with stochastic rounding
-// keeps single steps (every intermediate level would draw its own random
-// bits: 504 against 300 us).
+// step against 207 for single steps at 512^3), 3 for BF16 with stochastic
+// rounding (bound by the Philox draws: 281 against 300 us).
 int run_pass_steps(int dtype)
 {
     switch (g_kernel) {
@@ -522,7 +523,7 @@ int run_pass_steps(int dtype)
     case DIFF3D_KERNEL_ZMARCH: return 1;
     case DIFF3D_KERNEL_TB2: return 2;
     case DIFF3D_KERNEL_TBS: return g_pass_steps ? g_pass_steps : tbs_default_steps(dtype);
-    default: return dtype == DIFF3D_BF16 ? 1 : tbs_default_steps(dtype);
+    default: return tbs_default_steps(dtype);
     }
 }
 

@@ -757,6 +757,18 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
     static_assert(TX > 0 && TY > 0, "region too small for S steps");
     constexpr int K = (A0 + NTH - 1) / NTH;       // region points per thread
     __shared__ C lds[S][2][H0][W0];               // levels 0 .. S-1, double-buffered
+    // Stochastic rounding: the 64 points a wave holds for one (point slot k,
+    // level s) lie in at most 9 Philox blocks of 8 consecutive points (8 when
+    // rows start on multiples of 8: nx and TX multiples of 8), so a wave
+    // evaluates all NB*S*K blocks it needs in one Philox call (one block per
+    // lane) per plane iteration and passes the words through LDS.  Without
+    // room for them every lane draws its own block.
+    constexpr bool SR_B9 = Tr::sr && 9 * S * K <= 64;
+    constexpr bool SR_B8 = Tr::sr && !SR_B9 && 8 * S * K <= 64;
+    constexpr bool SR_BATCH = SR_B9 || SR_B8;
+    constexpr int NB = SR_B9 ? 9 : 8;
+    constexpr int NWAVE = NTH / 64;
+    __shared__ uint32_t srw[SR_BATCH ? NWAVE : 1][SR_BATCH ? 64 : 1][4];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
@@ -871,9 +883,71 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
     stage(0, 1, t0[1]);                     // plane p0 is read as "the previous iteration's" buffer
 
     // One plane iteration; PAR = (p - p0) & 1 selects the load slots.
+    // random words of this iteration's roundings (level s, slot k)
+    uint32_t rnd[SR_BATCH ? S : 1][SR_BATCH ? K : 1];
+    const bool batched = SR_B9 || (SR_B8 && nx % 8 == 0 && TX % 8 == 0);
+    auto draw = [&](int p) __attribute__((always_inline)) {
+        if constexpr (SR_BATCH) {
+            if (!batched) return;
+            const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+            // first block of each (s, k): from lane 0's point (wave-uniform)
+            size_t g0[S][K];
+#pragma unroll
+            for (int s = 1; s <= S; ++s)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const size_t g = gidx(k, p - s + 1) >> 3;
+                    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)g);
+                    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(g >> 32));
+                    g0[s - 1][k] = ((size_t)hi << 32) | lo;
+                }
+            // lane L computes block b of (s, k), L = ((s-1)*K + k)*NB + b
+            if (lane < NB * S * K) {
+                const int sk = lane / NB, b = lane % NB;
+                size_t g = 0;
+                int step = 0;
+#pragma unroll
+                for (int s = 1; s <= S; ++s)
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        if (sk == (s - 1) * K + k) {
+                            g = g0[s - 1][k] + (size_t)b;
+                            step = s - 1;
+                        }
+                SrState st = a.sr;
+                st.s0 = a.sr.s0 + (uint32_t)step;
+                st.s1 = a.sr.s1 + (st.s0 < a.sr.s0 ? 1u : 0u);
+                const u32x4 r = sr_block(st, g);
+                srw[wv][lane][0] = r.x;
+                srw[wv][lane][1] = r.y;
+                srw[wv][lane][2] = r.z;
+                srw[wv][lane][3] = r.w;
+            }
+            __builtin_amdgcn_wave_barrier();   // the wave's LDS writes precede its reads (in order per wave)
+#pragma unroll
+            for (int s = 1; s <= S; ++s)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const size_t i = gidx(k, p - s + 1);
+                    const int b = min(max((int)((i >> 3) - g0[s - 1][k]), 0), NB - 1);
+                    const unsigned j = (unsigned)(i & 7);
+                    const uint32_t w = srw[wv][((s - 1) * K + k) * NB + b][j >> 1];
+                    rnd[s - 1][k] = (j & 1) ? (w & 0xFFFF0000u) : (w << 16);
+                }
+            __builtin_amdgcn_wave_barrier();
+        }
+    };
+    auto rounding_at = [&](int k, int s, int z) __attribute__((always_inline)) -> uint32_t {
+        if constexpr (SR_BATCH)
+            return batched ? rnd[s - 1][k] : rounding(gidx(k, z), s - 1);
+        else
+            return rounding(gidx(k, z), s - 1);
+    };
+
     auto iteration = [&](auto par, int p) __attribute__((always_inline)) {
         constexpr int PAR = decltype(par)::value;
         constexpr int buf = PAR, rbuf = PAR ^ 1;
+        draw(p);
         // 1. loads two planes ahead
         load_T(p + 3, lt[PAR ^ 1]);
         load_Ci(p + 2, lc[PAR ^ 1]);
@@ -903,10 +977,10 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
                     const C yp = lds[s - 1][rbuf][rr[k] + 1][cc[k]];
                     const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, ci[s][k], a);
                     if (s < S) {
-                        v = Tr::load(Tr::store(w, rounding(gidx(k, z), s - 1)));
+                        v = Tr::load(Tr::store(w, rounding_at(k, s, z)));
                     } else if (z >= zb && z < ze && gx[k] >= ox0 && gx[k] < ox1 && gy[k] >= oy0 &&
                                gy[k] < oy1) {
-                        const S_ o = Tr::store(w, rounding(gidx(k, z), S - 1));
+                        const S_ o = Tr::store(w, rounding_at(k, S, z));
                         if (NT)
                             __builtin_nontemporal_store(o, a.T2 + gidx(k, z));
                         else

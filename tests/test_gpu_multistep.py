@@ -181,3 +181,21 @@ def test_tbs_adjoint_bit_exact(lib):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(to_host(gT0), gT0_ref)
     np.testing.assert_array_equal(to_host(gCi), gCi_ref)
+
+
+@pytest.mark.parametrize("S", [2, 3, 4])
+@pytest.mark.parametrize("shape", [(9, 40, 192), (9, 40, 190), (7, 33, 120), (6, 20, 64)])
+def test_tbs_stochastic_rounding_draws(lib, S, shape):
+    """Stochastic rounding in S-step passes draws the same Philox bits per
+    point and step as single steps, whether a wave's blocks are evaluated
+    together (rows on multiples of 8 or room for 9 blocks per level) or per
+    point."""
+    T0, Ci, s = _inputs(shape, seed=30 + S)
+    lib.set_kernel(lib.KERNEL_TBS)
+    lib.set_pass_steps(S)
+    lib.set_sr_seed(0xABCDEF12345, 77)
+    T = _gpu_run(lib, T0, Ci, s, 2 * S + 1, dtype=torch.bfloat16, rounding="sr")
+    lib.set_kernel(lib.KERNEL_NAIVE)
+    lib.set_sr_seed(0xABCDEF12345, 77)
+    R = _gpu_run(lib, T0, Ci, s, 2 * S + 1, dtype=torch.bfloat16, rounding="sr")
+    assert torch.equal(T, R)
