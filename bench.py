@@ -370,10 +370,25 @@ def main():
         oracle.forward(T0h, Cih, *sc, k)
         tc = time.perf_counter() - t1
         cpu_teff = bytes_step * k / tc / 1e9
+        # one thread: per-step time from runs of 1 and 2 steps
+        t1 = time.perf_counter()
+        oracle.forward(T0h, Cih, *sc, 1, threads=1)
+        s_one = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        oracle.forward(T0h, Cih, *sc, 2, threads=1)
+        s_step = max(time.perf_counter() - t1 - s_one, 1e-4)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": round(cpu_teff, 2), "unit": "GB/s", "cores": threads, "kind": "oracle",
                "sample": "oracle FP64 forward on the same bump 512^3 inputs, %d step(s) (plus its two "
                          "initial field copies), %.1f s" % (k, tc),
-               "t_step_s": round(tc / k, 4)}
+               "t_step_s": round(tc / k, 4), "cpu_model": model,
+               "single_thread": {"value": round(bytes_step / s_step / 1e9, 2), "unit": "GB/s",
+                                 "t_step_s": round(s_step, 3), "sample": "steps 1 and 2 of the same run"}}
         log("bench: cpu oracle", cpu)
 
     out = {

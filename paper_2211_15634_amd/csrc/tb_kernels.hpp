@@ -728,296 +728,3 @@ __global__ __launch_bounds__(64 * NW) void adj_tb2(AdjArgs<DT> a, int ntx, int n
 }
 
 }  // namespace diff3d
-
-namespace diff3d {
-
-// S time steps per pass over HBM.  A workgroup of NTH threads owns a W0 x H0
-// region in x-y; its output tile is the region without a border of S points
-// (TX = W0 - 2S by TY = H0 - 2S).  Level s (s = 0 .. S, level 0 = the input
-// T^k) is computed on the region without a border of s points, so level S
-// is the tile.  A region side that reaches the grid's boundary plane does
-// not shrink: the boundary values are the same at every level, so the
-// points next to it are computable at every level.  Regions therefore start
-// at the grid's edge (origin tx*TX, ty*TY) and the first and last tile of a
-// row or column output up to S-1 more points.  With W0 = 64 each wave holds whole region rows (coalesced).  Every thread keeps
-// the same region points at every level, so the z-history of a point (three
-// planes per level, four for the input with its prefetch) stays in that
-// thread's registers; x and y neighbours come from the level's plane staged
-// in LDS.  Per plane iteration p, level s is computed at plane p - s + 1 from
-// level s-1 (its planes p-s .. p-s+2), which is one LDS barrier per plane.
-// Intermediate levels are rounded exactly as storing them would round them,
-// so the result is bit-identical to S single steps.
-template <int DT, int S, int W0, int H0, int NTH, bool NT>
-__global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty, int zlen)
-{
-    using Tr = Traits<DT>;
-    using S_ = typename Tr::S;
-    using C = typename Tr::C;
-    constexpr int TX = W0 - 2 * S, TY = H0 - 2 * S, A0 = W0 * H0;
-    static_assert(TX > 0 && TY > 0, "region too small for S steps");
-    constexpr int K = (A0 + NTH - 1) / NTH;       // region points per thread
-    __shared__ C lds[S][2][H0][W0];               // levels 0 .. S-1, double-buffered
-    // Stochastic rounding: the 64 points a wave holds for one (point slot k,
-    // level s) lie in at most 9 Philox blocks of 8 consecutive points (8 when
-    // rows start on multiples of 8: nx and TX multiples of 8), so a wave
-    // evaluates all NB*S*K blocks it needs in one Philox call (one block per
-    // lane) per plane iteration and passes the words through LDS.  Without
-    // room for them every lane draws its own block.
-    constexpr bool SR_B9 = Tr::sr && 9 * S * K <= 64;
-    constexpr bool SR_B8 = Tr::sr && !SR_B9 && 8 * S * K <= 64;
-    constexpr bool SR_BATCH = SR_B9 || SR_B8;
-    constexpr int NB = SR_B9 ? 9 : 8;
-    constexpr int NWAVE = NTH / 64;
-    __shared__ uint32_t srw[SR_BATCH ? NWAVE : 1][SR_BATCH ? 64 : 1][4];
-
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
-    const int tx = (int)(t % (unsigned)ntx);
-    const int rest = (int)(t / (unsigned)ntx);
-    const int ty = rest % nty, tz = rest / nty;
-    const int x0 = tx * TX, y0 = ty * TY;         // region origin
-    const bool ex0 = x0 == 0, ex1 = x0 + W0 >= nx, ey0 = y0 == 0, ey1 = y0 + H0 >= ny;
-    // output tile: [ox0, ox1) x [oy0, oy1)
-    const int ox0 = ex0 ? 1 : x0 + S, ox1 = ex1 ? nx - 1 : x0 + W0 - S;
-    const int oy0 = ey0 ? 1 : y0 + S, oy1 = ey1 ? ny - 1 : y0 + H0 - S;
-    const int zb = 1 + tz * zlen;                 // output planes zb .. ze-1
-    const int ze = min(nz - 1, zb + zlen);
-    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-
-    // This thread's region points: region coordinates (r, c), global (x, y).
-    // Loads use addresses clamped into the grid (T) or onto a point the
-    // level-1 region needs (Ci), so they need no branch; values at points
-    // outside the grid are never used by an interior update.
-    int rr[K], cc[K], gx[K], gy[K];
-    size_t base[K], cbase[K];
-    bool live[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int idx = (int)threadIdx.x + k * NTH;
-        live[k] = idx < A0;
-        rr[k] = live[k] ? idx / W0 : 0;
-        cc[k] = live[k] ? idx % W0 : 0;
-        gx[k] = x0 + cc[k];
-        gy[k] = y0 + rr[k];
-        const int lx = min(max(gx[k], 0), nx - 1), ly = min(max(gy[k], 0), ny - 1);
-        base[k] = (size_t)lx + sy * (size_t)ly;
-        const int cx = min(max(x0 + min(max(cc[k], 1), W0 - 2), 0), nx - 1);
-        const int cy = min(max(y0 + min(max(rr[k], 1), H0 - 2), 0), ny - 1);
-        cbase[k] = (size_t)cx + sy * (size_t)cy;
-    }
-    // point k belongs to the region of level s (border of s points removed
-    // except on sides at the grid's boundary)
-    auto in_level = [&](int k, int s) __attribute__((always_inline)) {
-        return live[k] && (rr[k] >= s || ey0) && (rr[k] < H0 - s || ey1) && (cc[k] >= s || ex0) &&
-               (cc[k] < W0 - s || ex1);
-    };
-    auto interior_xy = [&](int k) __attribute__((always_inline)) {
-        return gx[k] >= 1 && gx[k] <= nx - 2 && gy[k] >= 1 && gy[k] <= ny - 2;
-    };
-    auto gidx = [&](int k, int z) __attribute__((always_inline)) {
-        return (size_t)gx[k] + sy * gy[k] + sz * z;
-    };
-    auto rounding = [&](size_t i, int step) __attribute__((always_inline)) -> uint32_t {
-        uint32_t rnd = 0;
-        if constexpr (Tr::sr) {
-            SrState st = a.sr;
-            st.s0 = a.sr.s0 + (uint32_t)step;
-            st.s1 = a.sr.s1 + (st.s0 < a.sr.s0 ? 1u : 0u);
-            rnd = sr_word(sr_block(st, i >> 3), (unsigned)(i & 7));
-        }
-        return rnd;
-    };
-    auto load_T = [&](int z, C (&dst)[K]) __attribute__((always_inline)) {
-        const size_t zo = sz * (size_t)min(max(z, 0), nz - 1);
-#pragma unroll
-        for (int k = 0; k < K; ++k) dst[k] = Tr::load(a.T[base[k] + zo]);
-    };
-    // Ci enters as lam*Ci, the product every update of that point forms
-    auto load_Ci = [&](int z, C (&dst)[K]) __attribute__((always_inline)) {
-        const size_t zo = sz * (size_t)min(max(z, 0), nz - 1);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const S_* p = a.Ci + cbase[k] + zo;
-            dst[k] = Tr::load(NT ? __builtin_nontemporal_load(p) : *p);
-        }
-    };
-    auto lam_ci = [&](C (&v)[K]) __attribute__((always_inline)) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = a.lam * v[k];
-    };
-    auto stage = [&](int lev, int buf, const C (&src)[K]) __attribute__((always_inline)) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (live[k]) lds[lev][buf][rr[k]][cc[k]] = src[k];
-    };
-
-    // Registers: level-0 planes p-1 .. p+1; for levels 1 .. S-1 the two
-    // planes below the one computed in this iteration (u[s-1][0] = z-1,
-    // u[s-1][1] = z, the new plane z+1 is the level's fresh output); lam*Ci
-    // at planes p, p-1, .., p-S+1 (ci[j] holds plane p+1-j); and two slots
-    // each for the loads in flight (T planes p+2 and p+3, Ci planes p+1 and
-    // p+2): a load is issued two plane iterations before its use.
-    C t0[3][K];
-    C u[S > 1 ? S - 1 : 1][2][K];
-    C ci[S + 1][K];
-    C lt[2][K], lc[2][K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-        for (int s = 0; s < (S > 1 ? S - 1 : 1); ++s)
-#pragma unroll
-            for (int i = 0; i < 2; ++i) u[s][i][k] = C(0);
-#pragma unroll
-        for (int j = 0; j <= S; ++j) ci[j][k] = C(0);
-    }
-
-    const int p0 = zb - S + 1;              // first plane of level 1
-    const int plast = ze + S - 2;           // last plane of level 1
-    load_T(p0 - 1, t0[0]);
-    load_T(p0, t0[1]);
-    load_T(p0 + 1, t0[2]);
-    load_T(p0 + 2, lt[0]);
-    load_Ci(p0, ci[1]);
-    lam_ci(ci[1]);
-    load_Ci(p0 + 1, lc[0]);
-    stage(0, 1, t0[1]);                     // plane p0 is read as "the previous iteration's" buffer
-
-    // One plane iteration; PAR = (p - p0) & 1 selects the load slots.
-    // random words of this iteration's roundings (level s, slot k)
-    uint32_t rnd[SR_BATCH ? S : 1][SR_BATCH ? K : 1];
-    const bool batched = SR_B9 || (SR_B8 && nx % 8 == 0 && TX % 8 == 0);
-    auto draw = [&](int p) __attribute__((always_inline)) {
-        if constexpr (SR_BATCH) {
-            if (!batched) return;
-            const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
-            // first block of each (s, k): from lane 0's point (wave-uniform)
-            size_t g0[S][K];
-#pragma unroll
-            for (int s = 1; s <= S; ++s)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const size_t g = gidx(k, p - s + 1) >> 3;
-                    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)g);
-                    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(g >> 32));
-                    g0[s - 1][k] = ((size_t)hi << 32) | lo;
-                }
-            // lane L computes block b of (s, k), L = ((s-1)*K + k)*NB + b
-            if (lane < NB * S * K) {
-                const int sk = lane / NB, b = lane % NB;
-                size_t g = 0;
-                int step = 0;
-#pragma unroll
-                for (int s = 1; s <= S; ++s)
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-                        if (sk == (s - 1) * K + k) {
-                            g = g0[s - 1][k] + (size_t)b;
-                            step = s - 1;
-                        }
-                SrState st = a.sr;
-                st.s0 = a.sr.s0 + (uint32_t)step;
-                st.s1 = a.sr.s1 + (st.s0 < a.sr.s0 ? 1u : 0u);
-                const u32x4 r = sr_block(st, g);
-                srw[wv][lane][0] = r.x;
-                srw[wv][lane][1] = r.y;
-                srw[wv][lane][2] = r.z;
-                srw[wv][lane][3] = r.w;
-            }
-            __builtin_amdgcn_wave_barrier();   // the wave's LDS writes precede its reads (in order per wave)
-#pragma unroll
-            for (int s = 1; s <= S; ++s)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const size_t i = gidx(k, p - s + 1);
-                    const int b = min(max((int)((i >> 3) - g0[s - 1][k]), 0), NB - 1);
-                    const unsigned j = (unsigned)(i & 7);
-                    const uint32_t w = srw[wv][((s - 1) * K + k) * NB + b][j >> 1];
-                    rnd[s - 1][k] = (j & 1) ? (w & 0xFFFF0000u) : (w << 16);
-                }
-            __builtin_amdgcn_wave_barrier();
-        }
-    };
-    auto rounding_at = [&](int k, int s, int z) __attribute__((always_inline)) -> uint32_t {
-        if constexpr (SR_BATCH)
-            return batched ? rnd[s - 1][k] : rounding(gidx(k, z), s - 1);
-        else
-            return rounding(gidx(k, z), s - 1);
-    };
-
-    auto iteration = [&](auto par, int p) __attribute__((always_inline)) {
-        constexpr int PAR = decltype(par)::value;
-        constexpr int buf = PAR, rbuf = PAR ^ 1;
-        draw(p);
-        // 1. loads two planes ahead
-        load_T(p + 3, lt[PAR ^ 1]);
-        load_Ci(p + 2, lc[PAR ^ 1]);
-        lds_barrier();
-        // 2. level 0, plane p+1, for level 1 of the next iteration
-        stage(0, buf, t0[2]);
-        // 3. levels 1 .. S at planes p, p-1, .., p-S+1
-        C prev[K];                          // level s-1 at plane z+1 (fresh output)
-#pragma unroll
-        for (int k = 0; k < K; ++k) prev[k] = t0[2][k];
-#pragma unroll
-        for (int s = 1; s <= S; ++s) {
-            const int z = p - s + 1;
-            const bool zact = z >= zb - (S - s) && z < ze + (S - s) && z >= 1 && z <= nz - 2;
-            C out[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                // level s-1 at planes z-1, z, z+1 for this point
-                const C zm = s == 1 ? t0[0][k] : u[s - 2][0][k];
-                const C ce = s == 1 ? t0[1][k] : u[s - 2][1][k];
-                const C zp = prev[k];
-                C v = ce;
-                if (zact && in_level(k, s) && interior_xy(k)) {
-                    const C xm = lds[s - 1][rbuf][rr[k]][cc[k] - 1];
-                    const C xp = lds[s - 1][rbuf][rr[k]][cc[k] + 1];
-                    const C ym = lds[s - 1][rbuf][rr[k] - 1][cc[k]];
-                    const C yp = lds[s - 1][rbuf][rr[k] + 1][cc[k]];
-                    const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, ci[s][k], a);
-                    if (s < S) {
-                        v = Tr::load(Tr::store(w, rounding_at(k, s, z)));
-                    } else if (z >= zb && z < ze && gx[k] >= ox0 && gx[k] < ox1 && gy[k] >= oy0 &&
-                               gy[k] < oy1) {
-                        const S_ o = Tr::store(w, rounding_at(k, S, z));
-                        if (NT)
-                            __builtin_nontemporal_store(o, a.T2 + gidx(k, z));
-                        else
-                            a.T2[gidx(k, z)] = o;
-                    }
-                }
-                out[k] = v;
-            }
-            if (s > 1) {
-                // level s-1's history moves up by one plane
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    u[s - 2][0][k] = u[s - 2][1][k];
-                    u[s - 2][1][k] = prev[k];
-                }
-            }
-            if (s < S) {
-                stage(s, buf, out);
-#pragma unroll
-                for (int k = 0; k < K; ++k) prev[k] = out[k];
-            }
-        }
-        // 4. shift level 0 and Ci; the older slot (plane p+2, Ci plane p+1) enters
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            t0[0][k] = t0[1][k];
-            t0[1][k] = t0[2][k];
-            t0[2][k] = lt[PAR][k];
-#pragma unroll
-            for (int j = S; j >= 2; --j) ci[j][k] = ci[j - 1][k];
-            ci[1][k] = a.lam * lc[PAR][k];
-        }
-    };
-    for (int p = p0; p <= plast; p += 2) {
-        iteration(std::integral_constant<int, 0>{}, p);
-        if (p + 1 <= plast) iteration(std::integral_constant<int, 1>{}, p + 1);
-    }
-}
-
-}  // namespace diff3d

@@ -84,14 +84,19 @@ def sample_points(shape, rng, k, include_edges=True):
     return pts
 
 
+def csrc_text() -> str:
+    """All host and kernel sources of the library, concatenated."""
+    import os
+    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2211_15634_amd", "csrc")
+    return "".join(open(os.path.join(d, f)).read() for f in sorted(os.listdir(d)) if f.endswith((".hip", ".hpp")))
+
+
 def instantiated_configs(kind: str, size: int):
     """The tile configurations the library instantiates (read from its
     source): kind "FWD" -> [(V, R, NW, NT)], kind "ADJ" -> [(V, R, NW)]."""
     import os
     import re
-    src = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2211_15634_amd",
-                       "csrc", "api.hip")
-    text = open(src).read().replace("\\\n", " ")
+    text = csrc_text().replace("\\\n", " ")
     m = re.search(r"#define DIFF3D_%s_CFGS_%d\(X\)(.*)" % (kind, size), text)
     assert m, (kind, size)
     return [tuple(int(v) for v in t.split(",")) for t in re.findall(r"X\(([\d ,]+)\)", m.group(1))]

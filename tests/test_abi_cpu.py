@@ -208,7 +208,8 @@ def test_default_tile_configurations_are_instantiated():
     import sys
     sys.path.insert(0, os.path.dirname(__file__))
     from helpers import instantiated_configs
-    src = open(os.path.join(ROOT, "paper_2211_15634_amd", "csrc", "api.hip")).read()
+    from helpers import csrc_text
+    src = csrc_text()
     sizes = {"F64": 8, "F32": 4, "BF16": 2, "BF16_RNE": 2}
     kinds = {"FwdDefaults": "FWD", "Tb2Defaults": "TB2", "AdjDefaults": "ADJ", "Adj2Defaults": "ADJ2"}
     found = 0
@@ -234,7 +235,8 @@ def test_multi_step_configurations_fit_and_defaults_are_instantiated():
     import sys
     sys.path.insert(0, os.path.dirname(__file__))
     from helpers import instantiated_configs
-    src = open(os.path.join(ROOT, "paper_2211_15634_amd", "csrc", "api.hip")).read()
+    from helpers import csrc_text
+    src = csrc_text()
     compute = {8: 8, 4: 4, 2: 4}          # LDS holds the arithmetic type
     for size in (8, 4, 2):
         cfgs = instantiated_configs("TBS", size)
@@ -264,7 +266,8 @@ def test_fused_reverse_configurations_fit_and_defaults_are_instantiated():
     import sys
     sys.path.insert(0, os.path.dirname(__file__))
     from helpers import instantiated_configs
-    src = open(os.path.join(ROOT, "paper_2211_15634_amd", "csrc", "api.hip")).read()
+    from helpers import csrc_text
+    src = csrc_text()
     for size in (8, 4):
         cfgs = instantiated_configs("REV", size)
         assert cfgs
