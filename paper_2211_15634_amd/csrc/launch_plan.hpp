@@ -125,7 +125,7 @@ inline int edge_tiles(int n, int w, int t) { return n <= w ? 1 : (n - w + t - 1)
 // z-chunking for kernels with few resident workgroups: equal-length blocks
 // run in rounds of `slots`, so pick the chunk count that minimises
 // rounds x (planes per chunk + `extra` halo planes), among counts that fill
-// the device (when the grid allows it).
+// at least 90% of the device (when the grid allows it).
 inline ZPlan plan_rounds(int ntx, int nty, int nzout, int zlen_req, int extra, long slots)
 {
     ZPlan p;
@@ -139,7 +139,7 @@ inline ZPlan plan_rounds(int ntx, int nty, int nzout, int zlen_req, int extra, l
         for (int nch = 1; nch <= nzout && nch <= 1024; ++nch) {
             const int zl = (nzout + nch - 1) / nch;
             const long blocks = tiles * ((nzout + zl - 1) / zl);
-            if (can_fill && blocks < slots) continue;
+            if (can_fill && blocks * 10 < slots * 9) continue;
             const long cost = ((blocks + slots - 1) / slots) * (long)(zl + extra);
             if (best < 0 || cost < best) {
                 best = cost;
