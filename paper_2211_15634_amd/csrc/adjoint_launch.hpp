@@ -147,11 +147,8 @@ constexpr int kMaxRevSteps = 3;
 
 // Measured: FP64 three-step passes on 64 x 16 regions take the 256^3 reverse
 // sweep (nt = 200, C = 14) from 40.3 ms (two-step kernels over recomputed
-// states) to 33 ms; FP32 three-step passes take the 1024^3 one (nt = 500,
-// C = 32) from 3.26 to 2.74 s.  With FP32 fields inside the last-level cache
-// (256^3: 67 MB) re-reading recomputed states is cheap and the two-step
-// kernels are as fast (21.5 vs 21.8 ms), so AUTO keeps them there.
-constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
+// states) to 32.2 ms; FP32 three-step passes take the 1024^3 one (nt = 500,
+// C = 32) from 3.26 to 2.74 s, and the 256^3 one from 21.5 to 21.2 ms.
 template <int DT>
 struct RevDefaults;
 template <> struct RevDefaults<DIFF3D_F64> {

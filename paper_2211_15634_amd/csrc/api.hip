@@ -244,8 +244,7 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
         if (rc) return rc;
     }
 
-    if (g_kernel == DIFF3D_KERNEL_TBS ||
-        (g_kernel == DIFF3D_KERNEL_AUTO && (dtype == DIFF3D_F64 || fb > kLastLevelCacheBytes))) {
+    if (g_kernel == DIFF3D_KERNEL_TBS || g_kernel == DIFF3D_KERNEL_AUTO) {
         // Fused reverse passes of P steps (the first pass of a segment takes
         // the remainder): only the states at pass starts are recomputed (by
         // forward passes of the same lengths), the pass recomputes the rest
