@@ -88,3 +88,27 @@ def test_bf16_sr_unbiased_on_slow_decay(lib):
     drop_rne = float(np.mean(to_host(to_dev(T0, torch.bfloat16))[c] - rne[c]))
     _report("sine96", {"drop_ref": drop_ref, "drop_sr": drop_sr, "drop_rne": drop_rne})
     assert abs(drop_sr - drop_ref) <= 0.1 * abs(drop_ref)
+
+
+def test_bump512_precision_forms_sampled(lib):
+    """The benchmark's 512^3 configuration (time loop with the default pass
+    lengths, nt = 100) in each storage form, at sampled points against the
+    FP64 oracle run on sub-boxes (exact at their centres, see
+    oracle_forward_at): FP32 within 1e-5 and BF16 with stochastic rounding
+    within 2e-2 relative; round-to-nearest is reported."""
+    from helpers import oracle_forward_at, sample_points
+    n, nt = 512, 100
+    T0, Ci = workloads.bump(n, n, n)
+    s = oracle.scalars(n, n, n, Ci)
+    pts = sample_points(T0.shape, np.random.default_rng(12), 5)
+    ref = oracle_forward_at(T0, Ci, s, nt, pts)
+    rec = {"points": len(pts)}
+    for name, tdt, rounding in (("fp32", torch.float32, "sr"), ("bf16_sr", torch.bfloat16, "sr"),
+                                ("bf16_rne", torch.bfloat16, "rne")):
+        got = _run(lib, T0, Ci, s, nt, tdt, rounding)
+        vals = np.array([got[p] for p in pts])
+        del got
+        rec[name + "_max_rel"] = float(np.max(np.abs(vals - ref) / np.maximum(np.abs(ref), 1e-300)))
+    _report("bump512_sampled", rec)
+    assert rec["fp32_max_rel"] <= 1e-5
+    assert rec["bf16_sr_max_rel"] <= 2e-2
