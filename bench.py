@@ -134,8 +134,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the 3-D diffusion step here runs on a single MI355X "
-              "(multi-GPU halo exchange is not part of this build); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the 3-D diffusion step on a single MI355X "
+              "(no multi-GPU halo exchange); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
