@@ -128,6 +128,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--large", action="store_true",
                     help="also run the 1024^3 FP32 forward + checkpointed adjoint form (nt=500, C=32, ~240 GB)")
+    ap.add_argument("--adjoint-probe", action="store_true",
+                    help="only run the 256^3 adjoint form (FP64 and FP32: forward with checkpoints, loss, "
+                         "reverse sweep), twice each (for kernel traces)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch a 1 GiB copy, the four-step, two-step and single-step kernels, 3 times "
                          "each (for counter runs)")
@@ -149,6 +152,28 @@ def main():
     n, nt = args.n, args.nt
     N = n * n * n
 
+    if args.adjoint_probe:
+        m, ntg, C = 256, 200, 14
+        for tdt in (torch.float64, torch.float32):
+            x, cc = workloads.uniform_const(m, m, m)
+            X0 = torch.from_numpy(x).to(dev, tdt)
+            Cg = torch.from_numpy(cc).to(dev, tdt)
+            Tt = torch.from_numpy(workloads.target(m, m, m)).to(dev, tdt)
+            sg = d3.problem_scalars(Cg)
+            scg = (sg["lam"], sg["dt"], sg["rdx"], sg["rdy"], sg["rdz"])
+            ws = torch.empty(d3.adjoint_workspace_bytes(X0.shape, ntg, C, tdt), dtype=torch.uint8, device=dev)
+            Tg, T2g = X0.clone(), torch.empty_like(X0)
+            seed, gT0, gCi = torch.empty_like(X0), torch.empty_like(X0), torch.empty_like(X0)
+            for _ in range(2):
+                Tg.copy_(X0)
+                d3.run(Tg, T2g, Cg, *scg, ntg, ckpt=ws, ckpt_every=C)
+                d3.loss(Tg, Tt, seed)
+                d3.adjoint_run(X0, Cg, seed, gT0, gCi, ws, True, *scg, ntg, C)
+            torch.cuda.synchronize()
+            del X0, Cg, Tt, ws, Tg, T2g, seed, gT0, gCi
+            torch.cuda.empty_cache()
+        log("adjoint probe done: 256^3 FP64 and FP32, nt=%d, C=%d, forward + reverse sweep twice each" % (ntg, C))
+        return
     if args.traffic_probe:
         # A copy of known size calibrates the FETCH_SIZE / WRITE_SIZE counters;
         # then the forward step kernel on the benchmark workload.

@@ -96,3 +96,38 @@ def test_python_binding_rejects(lib):
     ws = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(ValueError):
         lib.run(T, torch.empty_like(T), T.clone(), 1.0, 1e-3, 1.0, 1.0, 1.0, 10, ckpt=ws, ckpt_every=3)
+
+
+def test_side_stream(lib):
+    """Work is enqueued on the caller's current stream: the time loop and the
+    reverse sweep run inside a side stream give the default stream's bits."""
+    import oracle
+    from helpers import to_dev
+    shape = (20, 40, 96)
+    rng = np.random.default_rng(77)
+    T0 = rng.random(shape)
+    Ci = 0.5 * (1.0 + 0.5 * rng.random(shape))
+    g = rng.standard_normal(shape)
+    s = oracle.scalars(shape[2], shape[1], shape[0], Ci)
+    sc = (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+    nt, C = 30, 6
+
+    def run_all():
+        T, Cd, gd = to_dev(T0, torch.float64), to_dev(Ci, torch.float64), to_dev(g, torch.float64)
+        ws = torch.zeros(lib.adjoint_workspace_bytes(shape, nt, C, torch.float64), dtype=torch.uint8, device="cuda")
+        T2 = torch.empty_like(T)
+        Tn = T.clone()
+        lib.run(Tn, T2, Cd, *sc, nt, ckpt=ws, ckpt_every=C)
+        gT0, gCi = torch.empty_like(T), torch.empty_like(T)
+        lib.adjoint_run(T, Cd, gd, gT0, gCi, ws, True, *sc, nt, C)
+        return Tn, gT0, gCi
+
+    ref = run_all()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        out = run_all()
+    side.synchronize()
+    for a, b in zip(out, ref):
+        assert torch.equal(a, b)
