@@ -131,3 +131,33 @@ def test_side_stream(lib):
     side.synchronize()
     for a, b in zip(out, ref):
         assert torch.equal(a, b)
+
+
+def test_bench_json_contract():
+    """bench.py prints one JSON line with the keys and units of the contract:
+    whole-job T_eff, the roofline of its dominant kernel (measured on the
+    stream the kernel runs on) and, for one GPU only, no scaling claims."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--quick", "--steps", "2", "--warmup", "1"],
+                       cwd=root, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+                "vs_baseline", "dtype", "data", "config", "roofline"):
+        assert key in d, key
+    assert d["n_gpus"] == 1 and d["steps"] == 2 and d["warmup"] == 1 and d["unit"] == "GB/s"
+    assert d["value"] > 0 and d["higher_is_better"] is True and d["dtype"] == "f64"
+    rf = d["roofline"]
+    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
+    assert "workload" in d["config"]
+    # more than one GPU is refused with a message
+    r2 = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], cwd=root,
+                        capture_output=True, text=True, timeout=120)
+    assert r2.returncode != 0 and "one GPU" in r2.stderr
