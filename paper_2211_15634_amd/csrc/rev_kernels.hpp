@@ -62,7 +62,11 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
     constexpr int K = (A0 + NTH - 1) / NTH;       // region points per thread
     constexpr int NCI = 2 * S - 2;                // Ci planes held: p .. p-2S+3
     __shared__ C lf[S][2][A0];                    // F_0 .. F_{S-1}
-    __shared__ C lm[S][2][A0];                    // mu_0 .. mu_{S-1}
+    // mu planes carry a border of zeros (one row above and below, one column
+    // left and right): mu is zero beyond the grid, so a lambda stencil at the
+    // grid's edge reads its missing neighbours as stored zeros
+    constexpr int WP = W0 + 2, AP = WP * (H0 + 2);
+    __shared__ C lm[S][2][AP];                    // mu_0 .. mu_{S-1}
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
@@ -111,6 +115,43 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
 #pragma unroll
         for (int k = 0; k < K; ++k) dst[k] = Tr::load(f[base[k] + zo]);
     };
+    auto lap = [&](C t, C xm, C xp, C ym, C yp, C zm, C zp) __attribute__((always_inline)) -> C {
+        const C d2x = (xp - t) - (t - xm);
+        const C d2y = (yp - t) - (t - ym);
+        const C d2z = (zp - t) - (t - zm);
+        return (d2x * a.cx + d2y * a.cy) + d2z * a.cz;
+    };
+    auto stage = [&](C (&buf)[A0], const C (&src)[K]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (live[k]) buf[rr[k] * W0 + cc[k]] = src[k];
+    };
+    auto stage_mu = [&](C (&buf)[AP], const C (&src)[K]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (live[k]) buf[(rr[k] + 1) * WP + cc[k] + 1] = src[k];
+    };
+    // the zero border, written once (staging writes only the region's cells)
+    for (int i = (int)threadIdx.x; i < S * 2 * AP; i += NTH) {
+        const int q = i % AP, r = q / WP, c = q % WP;
+        if (r == 0 || r == H0 + 1 || c == 0 || c == WP - 1) (&lm[0][0][0])[i] = C(0);
+    }
+    // per-point conditions that do not change along z, one bit each
+    constexpr int G_BIT = 2 * S, O_BIT = 2 * S + 1, M_BIT = 2 * S + 2;
+    unsigned act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        unsigned b = 0;
+#pragma unroll
+        for (int f = 1; f <= S; ++f) b |= (in_level(k, f) && inner_xy(k)) ? 1u << (f - 1) : 0u;
+#pragma unroll
+        for (int j = 1; j <= S; ++j) b |= (in_level(k, j) && in_grid(k)) ? 1u << (S + j - 1) : 0u;
+        b |= (live[k] && inner_xy(k) && on_tile(k)) ? 1u << G_BIT : 0u;
+        b |= (in_level(k, S) && in_grid(k) && on_tile(k)) ? 1u << O_BIT : 0u;
+        b |= (live[k] && inner_xy(k)) ? 1u << M_BIT : 0u;
+        act[k] = b;
+    }
+    auto bit = [&](int k, int b) __attribute__((always_inline)) { return ((act[k] >> b) & 1u) != 0; };
     // gCi is read only where this workgroup writes it (tile, interior, plane
     // of this chunk): other workgroups update the rest concurrently
     auto load_g = [&](int z, C (&dst)[K]) __attribute__((always_inline)) {
@@ -118,24 +159,13 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             dst[k] = C(0);
-            if (zok && on_tile(k) && inner_xy(k)) dst[k] = Tr::load(a.gCi[gidx(k, z)]);
+            if (zok && bit(k, G_BIT)) dst[k] = Tr::load(a.gCi[gidx(k, z)]);
         }
-    };
-    auto lap = [&](C t, C xm, C xp, C ym, C yp, C zm, C zp) __attribute__((always_inline)) -> C {
-        const C d2x = (xp - t) - (t - xm);
-        const C d2y = (yp - t) - (t - ym);
-        const C d2z = (zp - t) - (t - zm);
-        return (d2x * a.cx + d2y * a.cy) + d2z * a.cz;
     };
     // mu of a point at plane z from lambda and Ci there (0 off the interior)
     auto mu_of = [&](int k, int z, C l, C ci) __attribute__((always_inline)) -> C {
-        const bool in = inner_xy(k) && z >= 1 && z <= nz - 2;
+        const bool in = bit(k, M_BIT) && z >= 1 && z <= nz - 2;
         return in ? (a.dtlam * ci) * l : C(0);
-    };
-    auto stage = [&](C (&buf)[A0], const C (&src)[K]) __attribute__((always_inline)) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (live[k]) buf[rr[k] * W0 + cc[k]] = src[k];
     };
 
     // registers (per point)
@@ -206,7 +236,7 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
                 const C ce = f == 1 ? t0[1][k] : uf[f - 2][1][k];
                 const C zp = prev[k];
                 C v = ce, lp = C(0);
-                if (zact && in_level(k, f) && inner_xy(k)) {
+                if (zact && bit(k, f - 1)) {
                     const int i = rr[k] * W0 + cc[k];
                     lp = lap(ce, lf[f - 1][rbuf][i - 1], lf[f - 1][rbuf][i + 1], lf[f - 1][rbuf][i - W0],
                              lf[f - 1][rbuf][i + W0], zm, zp);
@@ -238,7 +268,7 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
                 lprev[k] = ll[PAR][k];
                 mprev[k] = mu_of(k, z, lprev[k], cr[S - 2][k]);
             }
-            stage(lm[0][buf], mprev);
+            stage_mu(lm[0][buf], mprev);
         }
         // gCi of plane p-S+1 enters the partial sums
 #pragma unroll
@@ -254,15 +284,15 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
             for (int k = 0; k < K; ++k) {
                 const C lc0 = lh[j - 1][k];       // L_{j-1} at z
                 C v = lc0;
-                if (zact && in_level(k, j) && in_grid(k)) {
-                    const int i = rr[k] * W0 + cc[k];
+                if (zact && bit(k, S + j - 1)) {
+                    const int i = (rr[k] + 1) * WP + cc[k] + 1;
                     const C mc = mh[j - 1][1][k];
-                    const C xm = gx[k] > 0 ? lm[j - 1][rbuf][i - 1] : C(0);
-                    const C xp = gx[k] < nx - 1 ? lm[j - 1][rbuf][i + 1] : C(0);
-                    const C ym = gy[k] > 0 ? lm[j - 1][rbuf][i - W0] : C(0);
-                    const C yp = gy[k] < ny - 1 ? lm[j - 1][rbuf][i + W0] : C(0);
+                    const C xm = lm[j - 1][rbuf][i - 1];
+                    const C xp = lm[j - 1][rbuf][i + 1];
+                    const C ym = lm[j - 1][rbuf][i - WP];
+                    const C yp = lm[j - 1][rbuf][i + WP];
                     v = lc0 + lap(mc, xm, xp, ym, yp, mh[j - 1][0][k], mprev[k]);
-                    if (zin && zout && inner_xy(k) && on_tile(k))
+                    if (zin && zout && bit(k, G_BIT))
                         g[j - 1][k] = g[j - 1][k] + (a.dtlam * lc0) * lpr[j - 1][2 * j - 2][k];
                 }
                 out[k] = v;
@@ -281,13 +311,13 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
                     lprev[k] = out[k];
                     mprev[k] = mu_of(k, z, out[k], cr[ci_slot][k]);
                 }
-                stage(lm[j][buf], mprev);
+                stage_mu(lm[j][buf], mprev);
             } else if (zout) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    if (in_level(k, S) && in_grid(k) && on_tile(k)) {
+                    if (bit(k, O_BIT)) {
                         a.lout[gidx(k, z)] = Tr::store(out[k], 0);
-                        if (zin && inner_xy(k)) a.gCi[gidx(k, z)] = Tr::store(g[S - 1][k], 0);
+                        if (zin && bit(k, M_BIT)) a.gCi[gidx(k, z)] = Tr::store(g[S - 1][k], 0);
                     }
                 }
             }
