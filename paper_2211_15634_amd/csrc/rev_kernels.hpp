@@ -340,9 +340,25 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
                 for (int i = 2 * j - 2; i >= 1; --i) lpr[j - 1][i][k] = lpr[j - 1][i - 1][k];
         }
     };
-    for (int p = p0; p <= plast; p += 2) {
+    // Plane iterations, unrolled far enough that the z-history rings (up to
+    // six planes long) mostly rotate by renaming registers instead of
+    // copying them: four when a thread holds one point, two when it holds
+    // more (four would exceed 128 VGPRs there).
+    constexpr int UNR = K == 1 ? 4 : 2;
+    for (int p = p0; p <= plast; p += UNR) {
         iteration(std::integral_constant<int, 0>{}, p);
-        if (p + 1 <= plast) iteration(std::integral_constant<int, 1>{}, p + 1);
+        if constexpr (UNR == 2) {
+            if (p + 1 <= plast) iteration(std::integral_constant<int, 1>{}, p + 1);
+        } else {
+            // leaving the loop (rather than skipping the remaining copies)
+            // keeps the rings' register assignment fixed across the body
+            if (p + 1 > plast) break;
+            iteration(std::integral_constant<int, 1>{}, p + 1);
+            if (p + 2 > plast) break;
+            iteration(std::integral_constant<int, 0>{}, p + 2);
+            if (p + 3 > plast) break;
+            iteration(std::integral_constant<int, 1>{}, p + 3);
+        }
     }
 }
 
