@@ -92,6 +92,24 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
     auto interior_xy = [&](int k) __attribute__((always_inline)) {
         return gx[k] >= 1 && gx[k] <= nx - 2 && gy[k] >= 1 && gy[k] <= ny - 2;
     };
+    // The same conditions as a table of lane masks formed once outside the
+    // plane loop (combined without short-circuiting): fewer scalar
+    // instructions and no SGPR spills for FP32 and stochastically rounded
+    // BF16, measured 1.5% and 10% faster there.  FP64 and round-to-nearest
+    // BF16 evaluate them per use: measured 3% and 16% faster (the table
+    // takes the latter past 64 VGPRs, one workgroup per CU instead of two).
+    constexpr bool kMaskTable = DT == DIFF3D_F32 || DT == DIFF3D_BF16;
+    bool act[S + 1][K];
+#pragma unroll
+    for (int s = 1; s <= S; ++s)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            act[s][k] = live[k] & ((rr[k] >= s) | ey0) & ((rr[k] < H0 - s) | ey1) & ((cc[k] >= s) | ex0) &
+                        ((cc[k] < W0 - s) | ex1) & (gx[k] >= 1) & (gx[k] <= nx - 2) & (gy[k] >= 1) & (gy[k] <= ny - 2);
+    bool otile[K];                                // on this workgroup's output tile
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        otile[k] = (gx[k] >= ox0) & (gx[k] < ox1) & (gy[k] >= oy0) & (gy[k] < oy1);
     auto gidx = [&](int k, int z) __attribute__((always_inline)) {
         return (size_t)gx[k] + sy * gy[k] + sz * z;
     };
@@ -248,7 +266,7 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
                 const C ce = s == 1 ? t0[1][k] : u[s - 2][1][k];
                 const C zp = prev[k];
                 C v = ce;
-                if (zact && in_level(k, s) && interior_xy(k)) {
+                if (zact && (kMaskTable ? act[s][k] : in_level(k, s) && interior_xy(k))) {
                     const C xm = lds[s - 1][rbuf][rr[k]][cc[k] - 1];
                     const C xp = lds[s - 1][rbuf][rr[k]][cc[k] + 1];
                     const C ym = lds[s - 1][rbuf][rr[k] - 1][cc[k]];
@@ -256,8 +274,9 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
                     const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, ci[s][k], a);
                     if (s < S) {
                         v = Tr::load(Tr::store(w, rounding_at(k, s, z)));
-                    } else if (z >= zb && z < ze && gx[k] >= ox0 && gx[k] < ox1 && gy[k] >= oy0 &&
-                               gy[k] < oy1) {
+                    } else if (z >= zb && z < ze &&
+                               (kMaskTable ? otile[k]
+                                           : gx[k] >= ox0 && gx[k] < ox1 && gy[k] >= oy0 && gy[k] < oy1)) {
                         const S_ o = Tr::store(w, rounding_at(k, S, z));
                         if (NT)
                             __builtin_nontemporal_store(o, a.T2 + gidx(k, z));
