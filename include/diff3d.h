@@ -126,8 +126,8 @@ int diff3d_step2(void* T2, const void* T, const void* Ci, int nx, int ny, int nz
  * storing them would round them; stochastic rounding uses step indices
  * s .. s+nsteps-1 and advances the index by nsteps).  nsteps = 1 is
  * diff3d_step; nsteps = 2 runs the kernel of diff3d_step2 except under
- * DIFF3D_KERNEL_TBS (and, under DIFF3D_KERNEL_AUTO, for the BF16 forms).  Same buffer rules as diff3d_step; EINVAL for
- * nsteps out of range. */
+ * DIFF3D_KERNEL_TBS (and, under DIFF3D_KERNEL_AUTO, for the BF16 forms).
+ * Same buffer rules as diff3d_step; EINVAL for nsteps out of range. */
 int diff3d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
                  double dt, double rdx, double rdy, double rdz, int nsteps, int dtype, void* stream);
 

@@ -145,10 +145,10 @@ struct RKey {
 #define DIFF3D_REV_CFGS_4(X) X(2, 64, 32, 1024) X(3, 64, 32, 1024) X(3, 64, 16, 1024)
 constexpr int kMaxRevSteps = 3;
 
-// Measured: FP64 three-step passes on 64 x 16 regions take the 256^3 reverse
-// sweep (nt = 200, C = 14) from 40.3 ms (two-step kernels over recomputed
-// states) to 32.2 ms; FP32 three-step passes take the 1024^3 one (nt = 500,
-// C = 32) from 3.26 to 2.74 s, and the 256^3 one from 21.5 to 21.2 ms.
+// Measured reverse sweeps: 256^3, nt = 200, C = 14: FP64 40.3 ms with
+// two-step kernels over recomputed states, 23.9 ms with three-step passes on
+// 64 x 16 regions; FP32 21.5 ms and 14.4 ms (64 x 32 regions).  1024^3 FP32,
+// nt = 500, C = 32: 3.26 s and 1.87 s.
 template <int DT>
 struct RevDefaults;
 template <> struct RevDefaults<DIFF3D_F64> {

@@ -283,9 +283,8 @@ int step_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, in
 
 // n steps in one pass: a single step, the two-step kernel, or the S-step
 // kernel (always for n >= 3; for n = 2 when it is selected, and under AUTO
-// for the BF16 forms, where it is faster: 140 vs 340 us per step at 512^3
-// with round-to-nearest, 305 vs 584 with stochastic rounding; for FP64 and
-// FP32 the two-step kernel is faster).
+// for the BF16 forms, where it is about twice as fast per step at 512^3;
+// for FP64 and FP32 the two-step kernel is faster).
 int pass_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
                   double rdx, double rdy, double rdz, int n, uint64_t step_index, hipStream_t st)
 {
@@ -311,7 +310,7 @@ int tbs_default_steps(int dtype)
 // S-step kernel's measured best pass length: 4 for FP64, 3 for FP32, 2 for
 // BF16 with round-to-nearest (bound by ALU work more than bytes: 140 us per
 // step against 207 for single steps at 512^3), 3 for BF16 with stochastic
-// rounding (bound by the Philox draws: 281 against 300 us).
+// rounding (bound by the Philox draws: 253 against 300 us).
 int run_pass_steps(int dtype)
 {
     switch (g_kernel) {

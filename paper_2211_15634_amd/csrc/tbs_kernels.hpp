@@ -17,11 +17,11 @@ namespace diff3d {
 // not shrink: the boundary values are the same at every level, so the
 // points next to it are computable at every level.  Regions therefore start
 // at the grid's edge (origin tx*TX, ty*TY) and the first and last tile of a
-// row or column output up to S-1 more points.  With W0 = 64 each wave holds whole region rows (coalesced).  Every thread keeps
-// the same region points at every level, so the z-history of a point (three
-// planes per level, four for the input with its prefetch) stays in that
-// thread's registers; x and y neighbours come from the level's plane staged
-// in LDS.  Per plane iteration p, level s is computed at plane p - s + 1 from
+// row or column output up to S-1 more points.  With W0 = 64 each wave holds
+// whole region rows (coalesced).  Every thread keeps the same region points
+// at every level, so the z-history of a point (three planes per level, four
+// for the input with its prefetch) stays in that thread's registers; x and y
+// neighbours come from the level's plane staged in LDS.  Per plane iteration p, level s is computed at plane p - s + 1 from
 // level s-1 (its planes p-s .. p-s+2), which is one LDS barrier per plane.
 // Intermediate levels are rounded exactly as storing them would round them,
 // so the result is bit-identical to S single steps.
