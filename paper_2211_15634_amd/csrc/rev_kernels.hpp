@@ -152,10 +152,16 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
         act[k] = b;
     }
     auto bit = [&](int k, int b) __attribute__((always_inline)) { return ((act[k] >> b) & 1u) != 0; };
+    // z in [lo, hi) as one unsigned comparison (every range below has
+    // lo <= hi: chunks start inside the grid, zb < ze, nz >= 3)
+    auto in_range = [](int z, int lo, int hi) __attribute__((always_inline)) {
+        return (unsigned)(z - lo) < (unsigned)(hi - lo);
+    };
+    const int zi0 = max(zb, 1), zi1 = min(ze, nz - 1);   // chunk planes that are interior
     // gCi is read only where this workgroup writes it (tile, interior, plane
     // of this chunk): other workgroups update the rest concurrently
     auto load_g = [&](int z, C (&dst)[K]) __attribute__((always_inline)) {
-        const bool zok = z >= zb && z < ze && z >= 1 && z <= nz - 2;
+        const bool zok = in_range(z, zi0, zi1);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             dst[k] = C(0);
@@ -164,7 +170,7 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
     };
     // mu of a point at plane z from lambda and Ci there (0 off the interior)
     auto mu_of = [&](int k, int z, C l, C ci) __attribute__((always_inline)) -> C {
-        const bool in = bit(k, M_BIT) && z >= 1 && z <= nz - 2;
+        const bool in = bit(k, M_BIT) && in_range(z, 1, nz - 1);
         return in ? (a.dtlam * ci) * l : C(0);
     };
 
@@ -228,7 +234,7 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
         for (int f = 1; f <= S; ++f) {
             const int z = p - f + 1;
             // F_f is needed on planes [zb-(S-f), ze+(S-f)); Lap(F_{S-1}) on [zb, ze)
-            const bool zact = z >= zb - (S - f) && z < ze + (S - f) && z >= 1 && z <= nz - 2;
+            const bool zact = in_range(z, max(zb - (S - f), 1), min(ze + (S - f), nz - 1));
             C out[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -276,9 +282,9 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
 #pragma unroll
         for (int j = 1; j <= S; ++j) {
             const int z = p - S - j + 2;
-            const bool zact = z >= zb - (S - j) && z < ze + (S - j) && z >= 0 && z <= nz - 1;
-            const bool zin = z >= 1 && z <= nz - 2;
-            const bool zout = z >= zb && z < ze;
+            const bool zact = in_range(z, max(zb - (S - j), 0), min(ze + (S - j), nz));
+            const bool zin = in_range(z, 1, nz - 1);
+            const bool zout = in_range(z, zb, ze);
             C out[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -292,7 +298,7 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
                     const C ym = lm[j - 1][rbuf][i - WP];
                     const C yp = lm[j - 1][rbuf][i + WP];
                     v = lc0 + lap(mc, xm, xp, ym, yp, mh[j - 1][0][k], mprev[k]);
-                    if (zin && zout && bit(k, G_BIT))
+                    if (in_range(z, zi0, zi1) && bit(k, G_BIT))
                         g[j - 1][k] = g[j - 1][k] + (a.dtlam * lc0) * lpr[j - 1][2 * j - 2][k];
                 }
                 out[k] = v;

@@ -63,7 +63,7 @@ def _cases():
     out = []
     for name, size in (("f64", 8), ("f32", 4)):
         for cfg in instantiated_configs("REV", size):
-            for zlen in (0, 1, 3):
+            for zlen in (0, 1, 2, 3, 4):
                 out.append((name, cfg, zlen))
     return out
 
@@ -71,7 +71,9 @@ def _cases():
 @pytest.mark.parametrize("dtype,cfg,zlen", _cases())
 def test_rev_configs(lib, dtype, cfg, zlen):
     """Every instantiated fused-pass configuration and several z-chunk
-    lengths, with segments whose first pass is shorter (one or two steps)."""
+    lengths, with segments whose first pass is shorter (one or two steps).
+    A chunk of zlen planes takes zlen + 2S plane iterations, so zlen = 1..4
+    ends the four-way unrolled plane loop after each of its four copies."""
     S, W0, H0, NTH = cfg
     tdt = torch.float64 if dtype == "f64" else torch.float32
     T0, Ci, g, s = _inputs((13, 45, 150), seed=sum(cfg) + zlen)
