@@ -348,9 +348,9 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
     };
     // Plane iterations, unrolled far enough that the z-history rings (up to
     // six planes long) mostly rotate by renaming registers instead of
-    // copying them: four when a thread holds one point, two when it holds
-    // more (four would exceed 128 VGPRs there).
-    constexpr int UNR = K == 1 ? 4 : 2;
+    // copying them: four-way, except for two points per thread with three
+    // steps per pass, where four-way would exceed 128 VGPRs (two-way).
+    constexpr int UNR = (K > 1 && S > 2) ? 2 : 4;
     for (int p = p0; p <= plast; p += UNR) {
         iteration(std::integral_constant<int, 0>{}, p);
         if constexpr (UNR == 2) {
