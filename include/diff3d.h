@@ -59,7 +59,7 @@ typedef enum {
 
 typedef enum {
     DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps; in
-                                  diff3d_run S-step passes for FP64 (S = 4), FP32 (S = 3), BF16
+                                  diff3d_run S-step passes for FP64 (S = 4), FP32 (S = 4), BF16
                                   with stochastic rounding (S = 3) and BF16 with
                                   round-to-nearest (S = 2); in
                                   diff3d_adjoint_run fused three-step reverse passes */

@@ -186,10 +186,10 @@ template <int DT>
 struct TbsDefaults;
 template <> struct TbsDefaults<DIFF3D_F64> {
     static constexpr int S = 4;
-    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 0}, {3, 64, 32, 512, 0}, {4, 64, 32, 1024, 0}};
+    static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 512, 0}, {3, 64, 32, 1024, 0}, {4, 64, 32, 1024, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_F32> {
-    static constexpr int S = 3;
+    static constexpr int S = 4;
     static constexpr SKey key[5] = {{0}, {0}, {2, 64, 64, 1024, 0}, {3, 128, 32, 1024, 0}, {4, 64, 48, 768, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_BF16> {
@@ -307,7 +307,7 @@ int tbs_default_steps(int dtype)
 }
 
 // Steps per pass of diff3d_run for the selected kernel.  AUTO uses the
-// S-step kernel's measured best pass length: 4 for FP64, 3 for FP32, 2 for
+// S-step kernel's measured best pass length: 4 for FP64 and FP32, 2 for
 // BF16 with round-to-nearest (bound by ALU work more than bytes: 140 us per
 // step against 207 for single steps at 512^3), 3 for BF16 with stochastic
 // rounding (bound by the Philox draws: 253 against 300 us).
