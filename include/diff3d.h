@@ -59,10 +59,11 @@ typedef enum {
 
 typedef enum {
     DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps; in
-                                  diff3d_run S-step passes for FP64 (S = 4), FP32 (S = 4), BF16
-                                  with stochastic rounding (S = 3) and BF16 with
-                                  round-to-nearest (S = 2); in
-                                  diff3d_adjoint_run fused three-step reverse passes */
+                                  diff3d_run S-step passes for FP64 (S = 4), FP32 (S = 4;
+                                  3 on x-y planes above 768^2 points), BF16 with
+                                  stochastic rounding (S = 3) and BF16 with
+                                  round-to-nearest (S = 2); in diff3d_adjoint_run
+                                  fused three-step reverse passes */
     DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */
     DIFF3D_KERNEL_ZMARCH = 2,  /* x-y tiles marching along z, planes in registers and LDS */
     DIFF3D_KERNEL_TB2 = 3,     /* diff3d_run: two steps per pass (temporal blocking), z-march

@@ -30,7 +30,7 @@ int run_loop(int dtype, void* T, void* T2, const void* Ci, int nx, int ny, int n
     const size_t fbytes = npoints(nx, ny, nz) * elem_size(dtype);
     void* a = T;
     void* b = T2;
-    const int P = run_pass_steps(dtype);
+    const int P = run_pass_steps(dtype, nx, ny);
     for (int it = 0; it < nt;) {
         // P steps in one pass, shortened at the end and where a checkpoint
         // falls on a state inside the pass

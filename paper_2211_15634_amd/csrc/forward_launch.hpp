@@ -296,29 +296,36 @@ int pass_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, in
     return multi_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, step_index, st);
 }
 
-int tbs_default_steps(int dtype)
+// FP32 four-step passes lose to three-step ones on large x-y planes
+// (us per step, S = 3 / S = 4: 512^2 138 / 135, 768^2 497 / 461,
+// 896^2 732 / 755, 1024^2 1101 / 1410): three steps above 768^2 points.
+constexpr size_t kF32FourStepMaxPlane = (size_t)768 * 768;
+
+int tbs_default_steps(int dtype, int nx, int ny)
 {
     switch (dtype) {
     case DIFF3D_F64: return TbsDefaults<DIFF3D_F64>::S;
-    case DIFF3D_F32: return TbsDefaults<DIFF3D_F32>::S;
+    case DIFF3D_F32:
+        return (size_t)nx * (size_t)ny > kF32FourStepMaxPlane ? 3 : TbsDefaults<DIFF3D_F32>::S;
     case DIFF3D_BF16: return TbsDefaults<DIFF3D_BF16>::S;
     default: return TbsDefaults<DIFF3D_BF16_RNE>::S;
     }
 }
 
 // Steps per pass of diff3d_run for the selected kernel.  AUTO uses the
-// S-step kernel's measured best pass length: 4 for FP64 and FP32, 2 for
+// S-step kernel's measured best pass length: 4 for FP64 and FP32 (3 for
+// FP32 on planes above 768^2 points), 2 for
 // BF16 with round-to-nearest (bound by ALU work more than bytes: 140 us per
 // step against 207 for single steps at 512^3), 3 for BF16 with stochastic
 // rounding (bound by the Philox draws: 253 against 300 us).
-int run_pass_steps(int dtype)
+int run_pass_steps(int dtype, int nx, int ny)
 {
     switch (g_kernel) {
     case DIFF3D_KERNEL_NAIVE:
     case DIFF3D_KERNEL_ZMARCH: return 1;
     case DIFF3D_KERNEL_TB2: return 2;
-    case DIFF3D_KERNEL_TBS: return g_pass_steps ? g_pass_steps : tbs_default_steps(dtype);
-    default: return tbs_default_steps(dtype);
+    case DIFF3D_KERNEL_TBS: return g_pass_steps ? g_pass_steps : tbs_default_steps(dtype, nx, ny);
+    default: return tbs_default_steps(dtype, nx, ny);
     }
 }
 
