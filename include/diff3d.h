@@ -133,12 +133,14 @@ int diff3d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, int nz
                  double dt, double rdx, double rdy, double rdz, int nsteps, int dtype, void* stream);
 
 /* nt time steps with the buffer swap of Fig. 1.  First copies T's boundary
- * into T2, then alternates steps T -> T2 -> T ...  The result T_nt is always
- * left in T (one extra copy when nt is odd); T2 is scratch.
+ * into T2, then alternates passes (of one or more steps) T -> T2 -> T ...
+ * The result T_nt is always left in T (one extra copy when the last pass
+ * ends in T2); T2 is scratch.
  * Checkpoints: if ckpt is not NULL, the states T_{j*C} for j = 1 .. nck-1,
- * C = ckpt_every, nck = ceil(nt/C), are copied into consecutive fields of
- * ckpt (field j-1 holds T_{j*C}); this is the first part of the workspace
- * of diff3d_adjoint_run, which can then be called with ckpt_ready = 1.
+ * C = ckpt_every, nck = ceil(nt/C), are stored in consecutive fields of ckpt
+ * (field j-1 holds T_{j*C}, boundary included): the pass that reaches such a
+ * state writes it there; this is the first part of the workspace of
+ * diff3d_adjoint_run, which can then be called with ckpt_ready = 1.
  * ckpt_every must be >= 1 when ckpt is given.  nt = 0 leaves T unchanged. */
 int diff3d_run(void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt,
                double rdx, double rdy, double rdz, int nt, int dtype, void* stream, void* ckpt,
@@ -193,7 +195,10 @@ int diff3d_copy(void* dst, const void* src, size_t bytes, void* stream);
 int diff3d_set_kernel(int kernel);
 int diff3d_get_kernel(void);
 /* Steps per pass of diff3d_run under DIFF3D_KERNEL_TBS: 2 .. DIFF3D_MAX_PASS_STEPS,
- * or 0 for the default of each dtype; EINVAL otherwise (1 is DIFF3D_KERNEL_ZMARCH). */
+ * or 0 for the default of each dtype; EINVAL otherwise (1 is DIFF3D_KERNEL_ZMARCH).
+ * A set length gives passes of exactly that many steps, shortened only at a
+ * checkpoint or the end; the default splits each stretch between checkpoints
+ * into passes of near-equal length. */
 int diff3d_set_pass_steps(int nsteps);
 /* Seed of the stochastic rounding of DIFF3D_BF16 and the step index the
  * next diff3d_step uses; diff3d_run uses indices step0 .. step0+nt-1 and

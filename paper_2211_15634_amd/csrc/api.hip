@@ -18,8 +18,9 @@ using namespace diff3d;
 
 namespace {
 
-// The time loop of Fig. 1 on two buffers; checkpoint field j-1 receives
-// T_{j*C} for every j >= 1 with j*C <= klast.  With want_result the final
+// The time loop of Fig. 1: states alternate between T and T2, except that
+// the pass reaching T_{j*C} (j >= 1, j*C <= klast) writes it into checkpoint
+// field j-1, from which the next pass reads.  With want_result the final
 // state is left in T.
 int run_loop(int dtype, void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
              double rdy, double rdz, int nt, hipStream_t st, void* ckpt, int C, size_t field_stride, int klast,
@@ -28,31 +29,40 @@ int run_loop(int dtype, void* T, void* T2, const void* Ci, int nx, int ny, int n
     int rc = boundary_dispatch(dtype, T2, T, nx, ny, nz, st);
     if (rc) return rc;
     const size_t fbytes = npoints(nx, ny, nz) * elem_size(dtype);
-    void* a = T;
-    void* b = T2;
+    void* cur = T;                                // holds the current state
     const int P = run_pass_steps(dtype, nx, ny);
+    // a pass length set with diff3d_set_pass_steps is kept (P, P, .., rest)
+    const bool even = !(g_kernel == DIFF3D_KERNEL_TBS && g_pass_steps);
     for (int it = 0; it < nt;) {
-        // P steps in one pass, shortened at the end and where a checkpoint
-        // falls on a state inside the pass
-        int n = min(P, nt - it);
+        // Passes of at most P steps.  With the default pass length the
+        // stretch up to the next checkpointed state (or to nt) is split into
+        // passes of near-equal length: 14 steps with P = 4 as 4, 4, 3, 3
+        // rather than 4, 4, 4, 2 (short passes cost more per step).
+        int end = nt;
         if (ckpt) {
             const int next = (it / C + 1) * C;   // next checkpointed step
-            if (next <= klast && next - it < n) n = next - it;
+            if (next <= klast && next < end) end = next;
         }
-        rc = pass_dispatch(dtype, b, a, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, g_sr_step + (uint64_t)it, st);
-        if (rc) return rc;
-        void* s = a;
-        a = b;
-        b = s;
-        it += n;
-        const int k = it;
+        const int rem = end - it;
+        const int m = (rem + P - 1) / P;
+        const int n = even ? (rem + m - 1) / m : min(P, rem);
+        const int k = it + n;
+        // a pass ending on a checkpointed state writes it into its slot,
+        // whose boundary is set first (passes write interior points only;
+        // T's boundary is the initial one throughout)
+        void* dst = cur == T ? T2 : T;
         if (ckpt && k % C == 0 && k <= klast) {
-            rc = copy_bytes(static_cast<char*>(ckpt) + (size_t)(k / C - 1) * field_stride, a, fbytes, st);
+            dst = static_cast<char*>(ckpt) + (size_t)(k / C - 1) * field_stride;
+            rc = boundary_dispatch(dtype, dst, T, nx, ny, nz, st);
             if (rc) return rc;
         }
+        rc = pass_dispatch(dtype, dst, cur, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, g_sr_step + (uint64_t)it, st);
+        if (rc) return rc;
+        cur = dst;
+        it = k;
     }
     g_sr_step += (uint64_t)nt;
-    if (want_result && a != T) return copy_bytes(T, a, fbytes, st);
+    if (want_result && cur != T) return copy_bytes(T, cur, fbytes, st);
     return DIFF3D_OK;
 }
 
