@@ -199,3 +199,39 @@ def test_tbs_stochastic_rounding_draws(lib, S, shape):
     lib.set_sr_seed(0xABCDEF12345, 77)
     R = _gpu_run(lib, T0, Ci, s, 2 * S + 1, dtype=torch.bfloat16, rounding="sr")
     assert torch.equal(T, R)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nt,C", [(31, 7), (30, 14), (9, 4), (12, 6)])
+def test_default_passes_checkpoints(lib, dtype, nt, C):
+    """With the default pass length the time loop splits each stretch between
+    checkpoints into passes of near-equal length and the pass reaching a
+    checkpointed state writes it into its slot: every slot (boundary
+    included) and the final state equal single steps (FP64: the oracle)."""
+    tdt, rounding = TDT[dtype], "sr"
+    shape = (11, 37, 90)
+    T0, Ci, s = _inputs(shape, seed=nt + C)
+    nbytes = {"f64": 8, "f32": 4, "bf16": 2}[dtype]
+
+    def fill(kernel):
+        lib.set_kernel(kernel)
+        lib.set_sr_seed(5, 40)
+        ws = torch.zeros(lib.adjoint_workspace_bytes(shape, nt, C, tdt), dtype=torch.uint8, device="cuda")
+        T = to_dev(T0, tdt)
+        lib.run(T, torch.empty_like(T), to_dev(Ci, tdt), *_sc(s), nt, ckpt=ws, ckpt_every=C, rounding=rounding)
+        torch.cuda.synchronize()
+        stride = (T.numel() * nbytes + 255) // 256 * 256
+        slots = [ws[(j - 1) * stride:(j - 1) * stride + T.numel() * nbytes].view(tdt).reshape(shape).clone()
+                 for j in range(1, (nt + C - 1) // C)]
+        return T, slots
+
+    T, slots = fill(lib.KERNEL_AUTO)
+    if dtype == "f64":
+        np.testing.assert_array_equal(to_host(T), oracle.forward(T0, Ci, *_sc(s), nt))
+        for j, f in enumerate(slots, start=1):
+            np.testing.assert_array_equal(to_host(f), oracle.forward(T0, Ci, *_sc(s), j * C))
+    else:
+        R, rslots = fill(lib.KERNEL_ZMARCH)
+        assert torch.equal(T, R)
+        for f, g in zip(slots, rslots):
+            assert torch.equal(f, g)
