@@ -323,6 +323,29 @@ def main():
         torch.cuda.empty_cache()
         log("bench: precision forms", extra)
 
+        # ------------------------------------------------------ 64^3 FP64, nt = 100
+        # (the small parity workload: cache-resident and launch-bound, reported,
+        # not gated)
+        x, cc = workloads.uniform_const(64, 64, 64)
+        Ts = torch.from_numpy(x).to(dev, torch.float64)
+        Cs = torch.from_numpy(cc).to(dev, torch.float64)
+        ss = d3.problem_scalars(Cs)
+        scs = (ss["lam"], ss["dt"], ss["rdx"], ss["rdy"], ss["rdz"])
+        T2s = torch.empty_like(Ts)
+        for _ in range(3):
+            d3.run(Ts, T2s, Cs, *scs, 100)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            d3.run(Ts, T2s, Cs, *scs, 100)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts = e0.elapsed_time(e1) / 20 / 1e3 / 100
+        extra["t_step_uniform64_f64_us"] = round(ts * 1e6, 2)
+        extra["teff_uniform64_f64_GBps"] = round(3 * 8 * 64 ** 3 / ts / 1e9, 1)
+        del Ts, Cs, T2s
+        log("bench: 64^3 FP64 time loop %.2f us per step" % (ts * 1e6))
+
         # ------------------------------------------------------ adjoint ratio
         for tdt, tag in ((torch.float64, "f64"), (torch.float32, "f32")):
             m, ntg, C = 256, 200, 14
