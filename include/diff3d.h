@@ -62,7 +62,7 @@ typedef enum {
                                   diff3d_run S-step passes for FP64 (S = 4), FP32 (S = 4;
                                   3 on x-y planes above 768^2 points), BF16 with
                                   stochastic rounding (S = 3) and BF16 with
-                                  round-to-nearest (S = 2); in diff3d_adjoint_run
+                                  round-to-nearest (S = 4); in diff3d_adjoint_run
                                   fused three-step reverse passes */
     DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */
     DIFF3D_KERNEL_ZMARCH = 2,  /* x-y tiles marching along z, planes in registers and LDS */

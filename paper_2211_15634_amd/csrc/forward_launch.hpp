@@ -197,7 +197,7 @@ template <> struct TbsDefaults<DIFF3D_BF16> {
     static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 1024, 0}, {3, 64, 32, 1024, 0}, {4, 64, 32, 1024, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_BF16_RNE> {
-    static constexpr int S = 2;
+    static constexpr int S = 4;
     static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 1024, 0}, {3, 64, 32, 1024, 0}, {4, 64, 32, 1024, 0}};
 };
 
@@ -314,10 +314,10 @@ int tbs_default_steps(int dtype, int nx, int ny)
 
 // Steps per pass of diff3d_run for the selected kernel.  AUTO uses the
 // S-step kernel's measured best pass length: 4 for FP64 and FP32 (3 for
-// FP32 on planes above 768^2 points), 2 for
-// BF16 with round-to-nearest (bound by ALU work more than bytes: 140 us per
-// step against 207 for single steps at 512^3), 3 for BF16 with stochastic
-// rounding (bound by the Philox draws: 253 against 300 us).
+// FP32 on planes above 768^2 points), 4 for
+// BF16 with round-to-nearest (two workgroups per CU: 103 us per step against
+// 207 for single steps at 512^3), 3 for BF16 with stochastic rounding (bound
+// by the Philox draws: 253 against 300 us).
 int run_pass_steps(int dtype, int nx, int ny)
 {
     switch (g_kernel) {

@@ -25,8 +25,19 @@ namespace diff3d {
 // level s-1 (its planes p-s .. p-s+2), which is one LDS barrier per plane.
 // Intermediate levels are rounded exactly as storing them would round them,
 // so the result is bit-identical to S single steps.
+//
+// BF16 with round-to-nearest on 1024 threads and S >= 3 asks for eight waves
+// per SIMD (at most 64 VGPRs, two workgroups per CU; its LDS allows it): it
+// fits without spills, and four-step passes at 512^3 take 103 us per step
+// against 147 us at one workgroup per CU (two-step passes: 136 us).
+template <int DT, int S, int W0, int H0, int NTH>
+constexpr int tbs_min_waves()
+{
+    return (DT == DIFF3D_BF16_RNE && NTH == 1024 && S >= 3) ? 8 : 1;
+}
+
 template <int DT, int S, int W0, int H0, int NTH, bool NT>
-__global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty, int zlen)
+__global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void step_tbs(StepArgs<DT> a, int ntx, int nty, int zlen)
 {
     using Tr = Traits<DT>;
     using S_ = typename Tr::S;
@@ -94,11 +105,11 @@ __global__ __launch_bounds__(NTH) void step_tbs(StepArgs<DT> a, int ntx, int nty
     };
     // The same conditions as a table of lane masks formed once outside the
     // plane loop (combined without short-circuiting): fewer scalar
-    // instructions and no SGPR spills for FP32 and stochastically rounded
-    // BF16, measured 1.5% and 10% faster there.  FP64 and round-to-nearest
-    // BF16 evaluate them per use: measured 3% and 16% faster (the table
-    // takes the latter past 64 VGPRs, one workgroup per CU instead of two).
-    constexpr bool kMaskTable = DT == DIFF3D_F32 || DT == DIFF3D_BF16;
+    // instructions and no SGPR spills.  Measured faster for FP32 (1.5%),
+    // BF16 with stochastic rounding (10%) and BF16 with round-to-nearest at
+    // two workgroups per CU (8%); FP64 evaluates them per use (3% faster
+    // there, for no reason visible in the code).
+    constexpr bool kMaskTable = DT == DIFF3D_F32 || DT == DIFF3D_BF16 || DT == DIFF3D_BF16_RNE;
     bool act[S + 1][K];
 #pragma unroll
     for (int s = 1; s <= S; ++s)
