@@ -202,7 +202,7 @@ def test_tbs_stochastic_rounding_draws(lib, S, shape):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("nt,C", [(31, 7), (30, 14), (9, 4), (12, 6)])
+@pytest.mark.parametrize("nt,C", [(31, 7), (30, 14), (9, 4), (12, 6), (5, 1), (8, 8)])
 def test_default_passes_checkpoints(lib, dtype, nt, C):
     """With the default pass length the time loop splits each stretch between
     checkpoints into passes of near-equal length and the pass reaching a
