@@ -195,7 +195,8 @@ __global__ __launch_bounds__(64 * NW) void adj_zmarch(AdjArgs<DT> a, int ntx, in
 
     // One output plane z from planes z-1 (p0), z (p1, staged in LDS buffer
     // buf) and z+1 (p2); plane z+2 is prefetched into p3 and p2 is staged.
-    auto body = [&](int z, int buf, const Plane& p0, const Plane& p1, const Plane& p2, Plane& p3) __attribute__((always_inline)) {
+    auto body = [&](int z, int buf, const Plane& p0, const Plane& p1, const Plane& p2,
+                    Plane& p3) __attribute__((always_inline)) {
         const bool more = z + 1 < ze;
         if (more) load_plane(z + 2, p3);
         lds_barrier();

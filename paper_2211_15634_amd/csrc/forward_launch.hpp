@@ -58,7 +58,10 @@ struct FwdDefaults;
 template <> struct FwdDefaults<DIFF3D_F64> { static constexpr ZKey wide{2, 4, 4, 1}; static constexpr int zdef = 128; };
 template <> struct FwdDefaults<DIFF3D_F32> { static constexpr ZKey wide{4, 4, 4, 1}; static constexpr int zdef = 32; };
 template <> struct FwdDefaults<DIFF3D_BF16> { static constexpr ZKey wide{4, 1, 8, 0}; static constexpr int zdef = 32; };
-template <> struct FwdDefaults<DIFF3D_BF16_RNE> { static constexpr ZKey wide{4, 1, 8, 0}; static constexpr int zdef = 64; };
+template <> struct FwdDefaults<DIFF3D_BF16_RNE> {
+    static constexpr ZKey wide{4, 1, 8, 0};
+    static constexpr int zdef = 64;
+};
 constexpr ZKey kNarrow{1, 4, 4, 0};
 
 template <int DT, int V, int R, int NW, int NT>
@@ -100,8 +103,14 @@ template <int DT>
 struct Tb2Defaults;
 template <> struct Tb2Defaults<DIFF3D_F64> { static constexpr ZKey wide{2, 2, 8, 1}; static constexpr int zdef = 256; };
 template <> struct Tb2Defaults<DIFF3D_F32> { static constexpr ZKey wide{2, 2, 8, 1}; static constexpr int zdef = 128; };
-template <> struct Tb2Defaults<DIFF3D_BF16> { static constexpr ZKey wide{4, 2, 4, 1}; static constexpr int zdef = 128; };
-template <> struct Tb2Defaults<DIFF3D_BF16_RNE> { static constexpr ZKey wide{4, 2, 4, 1}; static constexpr int zdef = 128; };
+template <> struct Tb2Defaults<DIFF3D_BF16> {
+    static constexpr ZKey wide{4, 2, 4, 1};
+    static constexpr int zdef = 128;
+};
+template <> struct Tb2Defaults<DIFF3D_BF16_RNE> {
+    static constexpr ZKey wide{4, 2, 4, 1};
+    static constexpr int zdef = 128;
+};
 constexpr ZKey kNarrowTb2{1, 4, 4, 1};
 
 template <int DT, int V, int R, int NW, int NT, bool MID>

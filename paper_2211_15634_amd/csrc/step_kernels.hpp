@@ -166,7 +166,8 @@ __global__ __launch_bounds__(64 * NW) void step_zmarch(StepArgs<DT> a, int ntx, 
             for (int v = 0; v < V; ++v) lds[buf][yrow][1 + lane * V + v] = h.y[v];
         if (xrole) lds[buf][1 + lane][xcol] = h.x;
     };
-    auto compute = [&](int z, int buf, const Rows& prev, const Rows& cur, const Rows& nxt, const Rows& ci) __attribute__((always_inline)) {
+    auto compute = [&](int z, int buf, const Rows& prev, const Rows& cur, const Rows& nxt,
+                       const Rows& ci) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = yw + r;

@@ -142,7 +142,8 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
         vld(a.Ci, xl, yr1, z, yv, yload1, Str{});
         sld(a.Ci, xc1, yx, z, xs, xload1 && xmid);
     };
-    auto stage_A = [&](int buf, const Rows& own, const Vec& yv, const Vec& y2, C xs, C x2) __attribute__((always_inline)) {
+    auto stage_A = [&](int buf, const Rows& own, const Vec& yv, const Vec& y2, C xs,
+                       C x2) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll

@@ -21,8 +21,9 @@ namespace diff3d {
 // whole region rows (coalesced).  Every thread keeps the same region points
 // at every level, so the z-history of a point (three planes per level, four
 // for the input with its prefetch) stays in that thread's registers; x and y
-// neighbours come from the level's plane staged in LDS.  Per plane iteration p, level s is computed at plane p - s + 1 from
-// level s-1 (its planes p-s .. p-s+2), which is one LDS barrier per plane.
+// neighbours come from the level's plane staged in LDS.  Per plane iteration
+// p, level s is computed at plane p - s + 1 from level s-1 (its planes
+// p-s .. p-s+2), which is one LDS barrier per plane.
 // Intermediate levels are rounded exactly as storing them would round them,
 // so the result is bit-identical to S single steps.
 //
@@ -37,7 +38,8 @@ constexpr int tbs_min_waves()
 }
 
 template <int DT, int S, int W0, int H0, int NTH, bool NT>
-__global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void step_tbs(StepArgs<DT> a, int ntx, int nty, int zlen)
+__global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void step_tbs(StepArgs<DT> a, int ntx,
+                                                                                     int nty, int zlen)
 {
     using Tr = Traits<DT>;
     using S_ = typename Tr::S;

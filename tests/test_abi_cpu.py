@@ -214,7 +214,7 @@ def test_default_tile_configurations_are_instantiated():
     kinds = {"FwdDefaults": "FWD", "Tb2Defaults": "TB2", "AdjDefaults": "ADJ", "Adj2Defaults": "ADJ2"}
     found = 0
     for struct, kind in kinds.items():
-        for dt, V, R, NW, NT in re.findall(r"struct %s<DIFF3D_(\w+)> \{ static constexpr ZKey wide\{(\d+), (\d+), (\d+), (\d+)\}"
+        for dt, V, R, NW, NT in re.findall(r"struct %s<DIFF3D_(\w+)> \{\s*static constexpr ZKey wide\{(\d+), (\d+), (\d+), (\d+)\}"
                                             % struct, src):
             cfgs = instantiated_configs(kind, sizes[dt])
             key = (int(V), int(R), int(NW), int(NT)) if kind in ("FWD", "TB2") else (int(V), int(R), int(NW))
