@@ -55,6 +55,7 @@ def _load():
             lib.oracle_forward.argtypes = [dp, dp, dp, i, i, i, d, d, d, d, d, i, i]
             lib.oracle_forward.restype = i
             lib.oracle_reverse.argtypes = [dp, dp, dp, dp, dp, i, i, i, d, d, d, d, d, i, i, i]
+            lib.oracle_forward2d.argtypes = [dp, dp, dp, i, i, d, d, d, d, i, i]
             lib.oracle_reverse.restype = i
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = i
@@ -105,6 +106,31 @@ def forward(T0, Ci, lam: float, dt: float, rdx: float, rdy: float, rdz: float, n
     if rc != 0:
         raise ValueError("oracle_forward failed (%d)" % rc)
     return T
+
+
+def forward2d(T0, Ci, lam: float, dt: float, rdx: float, rdy: float, nt: int, threads: int = 0) -> np.ndarray:
+    """T_nt after nt steps of the 2-D form of the step (the Fig. 1 expression
+    without the z term) on an (ny, nx) array, boundary fixed."""
+    T0 = np.ascontiguousarray(T0, dtype=np.float64)
+    Ci = np.ascontiguousarray(Ci, dtype=np.float64)
+    if T0.ndim != 2 or Ci.shape != T0.shape:
+        raise ValueError("forward2d expects two (ny, nx) arrays")
+    ny, nx = T0.shape
+    T = np.empty_like(T0)
+    rc = _load().oracle_forward2d(_ptr(T), _ptr(T0), _ptr(Ci), nx, ny, lam, dt, rdx, rdy, int(nt), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_forward2d failed (%d)" % rc)
+    return T
+
+
+def scalars2d(nx: int, ny: int, Ci, lam: float = 1.0, lx: float = 1.0, ly: float = 1.0) -> dict:
+    """Driver scalars of the 2-D form: dx = lx/(nx-1), 1/dx, and
+    dt = min(dx^2, dy^2)/lam/max(Ci)/4.1 (the 3-D rule's divisor 6.1 = 2*3 +
+    0.1 becomes 2*2 + 0.1 in two dimensions)."""
+    dx, dy = lx / (nx - 1), ly / (ny - 1)
+    cmax = float(np.max(Ci))
+    dt = min(dx * dx, dy * dy) / lam / cmax / 4.1
+    return {"lam": lam, "dt": dt, "dx": dx, "dy": dy, "rdx": 1.0 / dx, "rdy": 1.0 / dy}
 
 
 def reverse(T0, Ci, g_nt, lam: float, dt: float, rdx: float, rdy: float, rdz: float, nt: int,

@@ -126,3 +126,26 @@ def complex_step_grad_Ci(T0, Ci, T_target, lam, dt, rdx, rdy, rdz, nt, h=1e-30):
         r = x - tgt
         g[j] = (0.5 * np.sum(r * r)).imag / h
     return g.reshape(Ci.shape)
+
+
+def exact_forward2d(T0, Ci, lam, dt, rdx, rdy, nt):
+    """Exact rational value of T_nt for the 2-D form on an (ny, nx) array,
+    second differences as A[i+1] - 2*A[i] + A[i-1]; returns an object array."""
+    ny, nx = T0.shape
+    T = [[Fraction(float(T0[y, x])) for x in range(nx)] for y in range(ny)]
+    C = [[Fraction(float(Ci[y, x])) for x in range(nx)] for y in range(ny)]
+    lam, dt = Fraction(lam), Fraction(dt)
+    wx, wy = Fraction(rdx) ** 2, Fraction(rdy) ** 2
+    for _ in range(nt):
+        new = [row[:] for row in T]
+        for y in range(1, ny - 1):
+            for x in range(1, nx - 1):
+                lap = (wx * (T[y][x + 1] - 2 * T[y][x] + T[y][x - 1])
+                       + wy * (T[y + 1][x] - 2 * T[y][x] + T[y - 1][x]))
+                new[y][x] = T[y][x] + dt * lam * C[y][x] * lap
+        T = new
+    out = np.empty((ny, nx), dtype=object)
+    for y in range(ny):
+        for x in range(nx):
+            out[y, x] = T[y][x]
+    return out

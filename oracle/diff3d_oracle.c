@@ -29,6 +29,11 @@
  *
  * Layout: linear index ix + nx*(iy + ny*iz), x fastest (Julia arrays are
  * column-major, so the first index is contiguous).
+ *
+ * The 2-D form (not printed in the paper, whose finite-difference modules
+ * come in 1-D, 2-D and 3-D): the same expression without the z term,
+ *       T2 = T + dt*(lam*Ci*(d2x(T)*(1/dx)^2 + d2y(T)*(1/dy)^2)),
+ * on interior points of an nx x ny grid (index ix + nx*iy), boundary fixed.
  */
 #include <math.h>
 #include <stdint.h>
@@ -216,5 +221,48 @@ int oracle_reverse(const double* T0, const double* Ci, const double* g_nt, doubl
     }
 
     free(kept); free(Tk); free(Tw); free(mu); free(lnext);
+    return 0;
+}
+
+/* The 2-D form of the step on interior points; the boundary of T2 is left
+ * alone.  Evaluated left to right: t + dt*((lam*Ci)*(d2x*cx + d2y*cy)). */
+static void step2d(double* T2, const double* T, const double* Ci, int nx, int ny, double lam, double dt,
+                   double rdx, double rdy)
+{
+    const double cx = rdx * rdx, cy = rdy * rdy;
+    const size_t sy = (size_t)nx;
+#pragma omp parallel for schedule(static)
+    for (int iy = 1; iy < ny - 1; ++iy)
+        for (int ix = 1; ix < nx - 1; ++ix) {
+            const size_t i = (size_t)ix + sy * (size_t)iy;
+            const double t = T[i];
+            const double d2x = (T[i + 1] - t) - (t - T[i - 1]);
+            const double d2y = (T[i + sy] - t) - (t - T[i - sy]);
+            T2[i] = t + dt * ((lam * Ci[i]) * (d2x * cx + d2y * cy));
+        }
+}
+
+/* T := T0 stepped nt times with the 2-D form, two buffers swapped after
+ * each step; the result is copied into T. */
+int oracle_forward2d(double* T, const double* T0, const double* Ci, int nx, int ny, double lam, double dt,
+                     double rdx, double rdy, int nt, int nthreads)
+{
+    if (nx < 3 || ny < 3 || nt < 0) return -1;
+    set_threads(nthreads);
+    const size_t n = (size_t)nx * ny;
+    double* T2 = (double*)malloc(n * sizeof(double));
+    if (!T2) return -2;
+    memcpy(T, T0, n * sizeof(double));
+    memcpy(T2, T0, n * sizeof(double));
+    double* a = T;
+    double* b = T2;
+    for (int it = 0; it < nt; ++it) {
+        step2d(b, a, Ci, nx, ny, lam, dt, rdx, rdy);
+        double* s = a;
+        a = b;
+        b = s;
+    }
+    if (a != T) memcpy(T, a, n * sizeof(double));
+    free(T2);
     return 0;
 }

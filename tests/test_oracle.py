@@ -358,3 +358,95 @@ def test_oracle_rejects_bad_sizes():
         oracle.forward(np.zeros((2, 4, 4)), np.zeros((2, 4, 4)), 1.0, 1e-3, 1.0, 1.0, 1.0, 1)
     with pytest.raises(ValueError):
         oracle.forward(np.zeros((4, 4, 4)), np.zeros((4, 4, 4)), 1.0, 1e-3, 1.0, 1.0, 1.0, -1)
+
+
+# ---------------------------------------------------------------- 2-D form
+# The same step without the z term on an (ny, nx) grid; pinned the same way.
+
+def _scal2(nx, ny, Ci, lx=1.0, ly=1.0, lam=1.0, divisor=None):
+    s = oracle.scalars2d(nx, ny, Ci, lam=lam, lx=lx, ly=ly)
+    if divisor is not None:
+        s["dt"] = s["dt"] * 4.1 / divisor
+    return s
+
+
+def _fwd2(T0, Ci, s, nt):
+    return oracle.forward2d(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], nt)
+
+
+def test_2d_scalars_closed_form():
+    nx, ny = 65, 33
+    Ci = np.full((ny, nx), 0.5)
+    Ci[3, 7] = 0.8                                 # max(Ci) over the whole array
+    s = _scal2(nx, ny, Ci, lx=1.0, ly=1.0)
+    assert s["dx"] == 1.0 / 64 and s["dy"] == 1.0 / 32
+    assert s["dt"] == (1.0 / 64) ** 2 / 1.0 / 0.8 / 4.1
+
+
+@pytest.mark.parametrize("shape,nt", [((4, 5), 1), ((4, 5), 3), ((5, 4), 2), ((6, 6), 2), ((3, 7), 2)])
+def test_2d_exact_rational_brute_force(shape, nt):
+    ny, nx = shape
+    rng = np.random.default_rng(31 + nx + 5 * ny)
+    T0 = rng.random((ny, nx))
+    Ci = 0.4 + 0.2 * rng.random((ny, nx))
+    s = _scal2(nx, ny, Ci, lx=1.0, ly=1.6)
+    T = _fwd2(T0, Ci, s, nt)
+    ex = brute.exact_forward2d(T0, Ci, s["lam"], s["dt"], s["rdx"], s["rdy"], nt)
+    scale = float(np.max(np.abs(ex.astype(np.float64))))
+    err = max(abs(float(ex[i] - Fraction(float(T[i])))) for i in np.ndindex(T.shape))
+    assert err <= 8 * nt * EPS * scale
+    mask = np.ones(T.shape, bool)
+    mask[1:-1, 1:-1] = False
+    assert np.array_equal(T[mask], T0[mask])
+
+
+@pytest.mark.parametrize("p,nt", [((1, 1), 25), ((3, 2), 25), ((31, 19), 25)])   # (31, 19): n - 2, near-checkerboard
+def test_2d_sine_mode_amplification(p, nt):
+    nx, ny = 33, 21
+    c = 0.5
+    Ci = np.full((ny, nx), c)
+    s = _scal2(nx, ny, Ci, lx=1.0, ly=1.4)
+    xs = np.sin(p[0] * np.pi * np.arange(nx) / (nx - 1))
+    ys = np.sin(p[1] * np.pi * np.arange(ny) / (ny - 1))
+    xs[0] = xs[-1] = 0.0
+    ys[0] = ys[-1] = 0.0
+    T0 = np.outer(ys, xs)
+    kap = (4 * math.sin(p[0] * math.pi / (2 * (nx - 1))) ** 2 * s["rdx"] ** 2
+           + 4 * math.sin(p[1] * math.pi / (2 * (ny - 1))) ** 2 * s["rdy"] ** 2)
+    g = 1.0 - s["dt"] * s["lam"] * c * kap
+    T = _fwd2(T0, Ci, s, nt)
+    err = np.max(np.abs(T - g ** nt * T0)) / np.max(np.abs(T0))
+    assert err <= 20 * nt * EPS, (g, err)
+
+
+def test_2d_constant_field_and_transpose():
+    rng = np.random.default_rng(8)
+    Ci = 0.5 + 0.5 * rng.random((9, 13))
+    s = _scal2(13, 9, Ci, lx=1.0, ly=0.7)
+    T0 = np.full((9, 13), 1.7)
+    assert np.array_equal(_fwd2(T0, Ci, s, 11), T0)
+    # swapping the axes (and their spacings) transposes the result bit for bit
+    T0 = rng.random((9, 13))
+    A = _fwd2(T0, Ci, s, 7)
+    B = oracle.forward2d(T0.T, Ci.T, s["lam"], s["dt"], s["rdy"], s["rdx"], 7)
+    assert np.array_equal(A, B.T)
+
+
+def test_2d_max_principle_and_negative_control():
+    nx, ny = 24, 17
+    rng = np.random.default_rng(5)
+    T0 = rng.random((ny, nx))
+    Ci = 0.25 + 0.5 * rng.random((ny, nx))
+    s = _scal2(nx, ny, Ci)
+    for nt in (1, 6, 50):
+        T = _fwd2(T0, Ci, s, nt)
+        assert T.min() >= T0.min() - 4 * EPS and T.max() <= T0.max() + 4 * EPS
+    # checkerboard on a square grid (dx = dy: centre weight 1 - 4/divisor):
+    # bounded at the 4.1 divisor, overshooting below 4
+    n = 17
+    cb = (np.indices((n, n)).sum(axis=0) % 2).astype(np.float64)
+    Cc = np.full((n, n), 0.5)
+    ok = _fwd2(cb, Cc, _scal2(n, n, Cc), 3)
+    assert ok.min() >= -4 * EPS and ok.max() <= 1 + 4 * EPS
+    bad = _fwd2(cb, Cc, _scal2(n, n, Cc, divisor=3.5), 3)
+    assert bad.min() < -1e-3 or bad.max() > 1 + 1e-3
