@@ -346,6 +346,28 @@ def main():
         del Ts, Cs, T2s
         log("bench: 64^3 FP64 time loop %.2f us per step" % (ts * 1e6))
 
+        # ------------------------------------------------------ 2-D form, 8192^2 FP64, nt = 100
+        n2 = 8192
+        x2 = np.random.default_rng(0).random((n2, n2))
+        T2d = torch.from_numpy(x2).to(dev)
+        C2d = torch.full_like(T2d, 0.5)
+        dx2 = 1.0 / (n2 - 1)
+        sc2 = (1.0, dx2 * dx2 / 1.0 / 0.5 / 4.1, 1.0 / dx2, 1.0 / dx2)
+        S2d = torch.empty_like(T2d)
+        d3.run2d(T2d, S2d, C2d, *sc2, 10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            d3.run2d(T2d, S2d, C2d, *sc2, 100)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts = e0.elapsed_time(e1) / 3 / 1e3 / 100
+        extra["t_step_2d_8192_f64_us"] = round(ts * 1e6, 2)
+        extra["teff_2d_8192_f64_GBps"] = round(3 * 8 * n2 * n2 / ts / 1e9, 1)
+        del T2d, C2d, S2d, x2
+        torch.cuda.empty_cache()
+        log("bench: 2-D 8192^2 FP64 %.1f us per step" % (ts * 1e6))
+
         # ------------------------------------------------------ adjoint ratio
         for tdt, tag in ((torch.float64, "f64"), (torch.float32, "f32")):
             m, ntg, C = 256, 200, 14

@@ -205,6 +205,23 @@ int diff3d_set_pass_steps(int nsteps);
  * advances the index by nt, diff3d_step by 1. */
 void diff3d_set_sr_seed(uint64_t seed, uint64_t step0);
 
+/* The 2-D form of the step (not printed in the paper, whose Fig. 1 is the
+ * 3-D solver): the Fig. 1 expression without the z term,
+ *   T2 = T + dt*((lam*Ci)*(d2x(T)*rdx^2 + d2y(T)*rdy^2))   on interior points,
+ * on an nx x ny grid, linear index x + nx*y (x fastest); T2's boundary is not
+ * written.  dtype DIFF3D_F64 or DIFF3D_F32 (DIFF3D_EDTYPE otherwise); nx, ny
+ * >= 3; T2 must not overlap T or Ci (EINVAL).  Device pointers, enqueued on
+ * `stream`. */
+int diff2d_step(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt,
+                double rdx, double rdy, int dtype, void* stream);
+
+/* nt steps of the 2-D form with the buffer swap: T2 = copy(T) first, then
+ * T -> T2 -> T ...; the result T_nt is left in T (T2 is scratch).  Same
+ * argument rules as diff2d_step, plus nt >= 0 and T not overlapping Ci;
+ * nt = 0 leaves T unchanged. */
+int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
+               double rdy, int nt, int dtype, void* stream);
+
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the counter-based
  * generator behind the stochastic rounding: out = bijection of ctr under
  * key.  Host function (same code as on the device), for tests. */

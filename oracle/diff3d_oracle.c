@@ -30,8 +30,8 @@
  * Layout: linear index ix + nx*(iy + ny*iz), x fastest (Julia arrays are
  * column-major, so the first index is contiguous).
  *
- * The 2-D form (not printed in the paper, whose finite-difference modules
- * come in 1-D, 2-D and 3-D): the same expression without the z term,
+ * The 2-D form (not printed in the paper, whose Fig. 1 is the 3-D solver):
+ * the same expression without the z term,
  *       T2 = T + dt*(lam*Ci*(d2x(T)*(1/dx)^2 + d2y(T)*(1/dy)^2)),
  * on interior points of an nx x ny grid (index ix + nx*iy), boundary fixed.
  */

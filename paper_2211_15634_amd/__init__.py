@@ -60,6 +60,8 @@ _SIGS = {
     "diff3d_set_pass_steps": ([_i], _i),
     "diff3d_set_sr_seed": ([ctypes.c_uint64, ctypes.c_uint64], None),
     "diff3d_philox4x32_10": ([_u32p, _u32p, _u32p], None),
+    "diff2d_step": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _vp], _i),
+    "diff2d_run": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _vp], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -178,6 +180,39 @@ def problem_scalars(Ci: torch.Tensor, lam: float = 1.0, lx: float = 1.0, ly: flo
     nz, ny, nx = Ci.shape
     cimax = float(field_max(Ci).item())
     return scalars(nx, ny, nz, cimax, lam=lam, lx=lx, ly=ly, lz=lz)
+
+
+def _field2d(t: torch.Tensor, name: str, like: torch.Tensor | None = None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA/HIP tensor" % name)
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous (ny, nx) tensor" % name)
+    if like is not None and (t.shape != like.shape or t.dtype != like.dtype or t.device != like.device):
+        raise ValueError("%s must match shape/dtype/device of the other fields" % name)
+    return t
+
+
+def step2d(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float,
+           rdy: float) -> None:
+    """One step of the 2-D form: interior of T2 from T and Ci, (ny, nx) fields."""
+    _field2d(T, "T")
+    _field2d(T2, "T2", T)
+    _field2d(Ci, "Ci", T)
+    ny, nx = T.shape
+    with _on(T):
+        _check(_lib.diff2d_step(_p(T2), _p(T), _p(Ci), nx, ny, lam, dt, rdx, rdy, _code(T), _stream(T)), "step2d")
+
+
+def run2d(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
+          nt: int) -> None:
+    """nt steps of the 2-D form with the swap; the result is left in T."""
+    _field2d(T, "T")
+    _field2d(T2, "T2", T)
+    _field2d(Ci, "Ci", T)
+    ny, nx = T.shape
+    with _on(T):
+        _check(_lib.diff2d_run(_p(T), _p(T2), _p(Ci), nx, ny, lam, dt, rdx, rdy, int(nt), _code(T), _stream(T)),
+               "run2d")
 
 
 def step(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,

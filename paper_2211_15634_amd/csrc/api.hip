@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include "adjoint_launch.hpp"
+#include "diff2d_launch.hpp"
 #include "diff3d.h"
 #include "forward_launch.hpp"
 #include "host_common.hpp"
@@ -365,6 +366,48 @@ void diff3d_set_sr_seed(uint64_t seed, uint64_t step0)
 {
     g_sr_seed = seed;
     g_sr_step = step0;
+}
+
+// ------------------------------------------------------------- 2-D form
+
+static int check2d(const void* T2, const void* T, const void* Ci, int nx, int ny, int dtype)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (dtype != DIFF3D_F64 && dtype != DIFF3D_F32) return DIFF3D_EDTYPE;
+    if (!T2 || !T || !Ci || nx < 3 || ny < 3 || (size_t)nx * (size_t)ny >= kMaxPoints) return DIFF3D_EINVAL;
+    const size_t fb = (size_t)nx * ny * elem_size(dtype);
+    if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb)) return DIFF3D_EINVAL;
+    return DIFF3D_OK;
+}
+
+int diff2d_step(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
+                double rdy, int dtype, void* stream)
+{
+    const int rc = check2d(T2, T, Ci, nx, ny, dtype);
+    if (rc) return rc;
+    return step2d_dispatch(dtype, T2, T, Ci, nx, ny, lam, dt, rdx, rdy, as_stream(stream));
+}
+
+int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, double dt, double rdx, double rdy,
+               int nt, int dtype, void* stream)
+{
+    int rc = check2d(T2, T, Ci, nx, ny, dtype);
+    if (rc) return rc;
+    const size_t fb = (size_t)nx * ny * elem_size(dtype);
+    if (nt < 0 || overlap(T, fb, Ci, fb)) return DIFF3D_EINVAL;
+    if (nt == 0) return DIFF3D_OK;
+    hipStream_t st = as_stream(stream);
+    rc = copy_bytes(T2, T, fb, st);               // T2 = copy(T): both buffers carry T's boundary
+    void* a = T;
+    void* b = T2;
+    for (int it = 0; it < nt && !rc; ++it) {
+        rc = step2d_dispatch(dtype, b, a, Ci, nx, ny, lam, dt, rdx, rdy, st);
+        void* s = a;
+        a = b;
+        b = s;
+    }
+    if (!rc && a != T) rc = copy_bytes(T, a, fb, st);
+    return rc;
 }
 
 void diff3d_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])

@@ -1,0 +1,75 @@
+// The 2-D form of the step: the Fig. 1 expression without the z term,
+//   T2 = T + dt*((lam*Ci)*(d2x(T)*cx + d2y(T)*cy))   on interior points,
+// on an nx x ny grid (index x + nx*y), boundary values never written.
+#pragma once
+
+#include "common.hpp"
+
+namespace diff3d {
+
+template <int DT>
+struct Step2dArgs {
+    using S = typename Traits<DT>::S;
+    using C = typename Traits<DT>::C;
+    S* __restrict__ T2;
+    const S* __restrict__ T;
+    const S* __restrict__ Ci;
+    int nx, ny;
+    C lam, dt, cx, cy;
+};
+
+// One wave64 owns a strip of 64 consecutive x points (lane l: x = 64*strip
+// + l) and marches along y over `ylen` output rows.  Rows y-1, y, y+1 of its
+// point live in registers and row y+2 is loaded one iteration ahead, so the
+// y neighbours never leave the thread; the x neighbours are the adjacent
+// lanes' values (cross-lane moves), the strip's two outer neighbours one
+// extra load per row (lanes 1..63 all load the same address, lane 0 the
+// point left of the strip).  Waves are independent: no LDS, no barrier.
+// Loads are clamped into the grid; values of points outside it are never
+// used by an interior update.
+template <int DT, int WPB>
+__global__ __launch_bounds__(64 * WPB) void step2d_ymarch(Step2dArgs<DT> a, int nstrips, int nchunks, int ylen)
+{
+    using Tr = Traits<DT>;
+    using S_ = typename Tr::S;
+    using C = typename Tr::C;
+    const int lane = (int)(threadIdx.x & 63);
+    const int wid = (int)blockIdx.x * WPB + (int)(threadIdx.x >> 6);
+    if (wid >= nstrips * nchunks) return;         // whole waves
+    const int nx = a.nx, ny = a.ny;
+    const int strip = wid % nstrips, chunk = wid / nstrips;
+    const int ys = 1 + chunk * ylen, ye = min(ny - 1, ys + ylen);   // output rows ys .. ye-1
+    if (ys >= ye) return;                         // whole waves
+    const int x = strip * 64 + lane;
+    const int xc = min(x, nx - 1);
+    const int xh = lane == 0 ? max(x - 1, 0) : min(strip * 64 + 64, nx - 1);
+    const bool interior_x = x >= 1 && x <= nx - 2;
+    const size_t sy = (size_t)nx;
+    auto ld = [&](const S_* p, int y, int xx) __attribute__((always_inline)) -> C {
+        return Tr::load(p[(size_t)xx + sy * (size_t)y]);
+    };
+    C rm = ld(a.T, ys - 1, xc), rc = ld(a.T, ys, xc), rp = ld(a.T, ys + 1, xc);
+    C hc = ld(a.T, ys, xh), cc = ld(a.Ci, ys, xc);
+    for (int y = ys; y < ye; ++y) {
+        // next row's values, one iteration ahead
+        const C rn = ld(a.T, min(y + 2, ny - 1), xc);
+        const C hn = ld(a.T, y + 1, xh);
+        const C cn = ld(a.Ci, y + 1, xc);
+        C xm = __shfl_up(rc, 1);
+        C xp = __shfl_down(rc, 1);
+        if (lane == 0) xm = hc;
+        if (lane == 63) xp = hc;
+        const C t = rc;
+        const C d2x = (xp - t) - (t - xm);
+        const C d2y = (rp - t) - (t - rm);
+        const C w = t + a.dt * ((a.lam * cc) * (d2x * a.cx + d2y * a.cy));
+        if (interior_x) a.T2[(size_t)x + sy * (size_t)y] = Tr::store(w, 0);
+        rm = rc;
+        rc = rp;
+        rp = rn;
+        hc = hn;
+        cc = cn;
+    }
+}
+
+}  // namespace diff3d

@@ -20,7 +20,7 @@ d3 = pytest.importorskip("paper_2211_15634_amd")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(diff3d_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(diff[23]d_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported():
@@ -285,3 +285,20 @@ def test_fused_reverse_configurations_fit_and_defaults_are_instantiated():
             found += 1
         assert 2 <= int(S) <= len(tup) - 1
     assert found == 4
+
+
+def test_2d_argument_validation_without_gpu():
+    """The 2-D entry points reject bad arguments before any launch."""
+    lib = d3._lib
+    p = ctypes.c_void_p(4096)
+    q = ctypes.c_void_p(1 << 30)
+    r = ctypes.c_void_p(1 << 31)
+    sc = (1.0, 1e-5, 10.0, 10.0)
+    assert lib.diff2d_step(p, q, r, 8, 8, *sc, d3.BF16, None) == d3.EDTYPE
+    assert lib.diff2d_step(p, q, r, 8, 8, *sc, 9, None) == d3.EDTYPE
+    assert lib.diff2d_step(None, q, r, 8, 8, *sc, d3.F64, None) == d3.EINVAL
+    assert lib.diff2d_step(p, q, r, 2, 8, *sc, d3.F64, None) == d3.EINVAL
+    assert lib.diff2d_step(p, p, r, 8, 8, *sc, d3.F64, None) == d3.EINVAL
+    assert lib.diff2d_run(p, q, r, 8, 8, *sc, -1, d3.F64, None) == d3.EINVAL
+    assert lib.diff2d_run(p, q, p, 8, 8, *sc, 3, d3.F64, None) == d3.EINVAL
+    assert lib.diff2d_run(p, q, r, 8, 8, *sc, 0, d3.F32, None) == d3.OK

@@ -1,0 +1,90 @@
+"""The 2-D form of the step (the Fig. 1 expression without the z term) on the
+GPU: FP64 bit-identical to the oracle, FP32 within its error bound."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _inputs(shape, seed=0):
+    ny, nx = shape
+    rng = np.random.default_rng(500 + seed)
+    T0 = rng.random(shape)
+    Ci = 0.5 * (1.0 + 0.5 * rng.random(shape))
+    s = oracle.scalars2d(nx, ny, Ci, lx=1.0, ly=1.3)
+    return T0, Ci, s
+
+
+def _sc(s):
+    return (s["lam"], s["dt"], s["rdx"], s["rdy"])
+
+
+SHAPES = [(3, 3), (4, 5), (5, 70), (67, 3), (3, 64), (3, 65), (130, 129), (64, 257), (200, 63), (33, 1000)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_step_bitwise_and_boundary_untouched(lib, shape):
+    T0, Ci, s = _inputs(shape, seed=shape[0] + shape[1])
+    T = torch.from_numpy(T0).cuda()
+    C = torch.from_numpy(Ci).cuda()
+    T2 = torch.full_like(T, float("nan"))
+    b = torch.ones(shape, dtype=torch.bool)
+    b[1:-1, 1:-1] = False
+    b = b.cuda()
+    T2[b] = -5.0
+    lib.step2d(T2, T, C, *_sc(s))
+    torch.cuda.synchronize()
+    ref = oracle.forward2d(T0, Ci, *_sc(s), 1)
+    got = T2.cpu().numpy()
+    inner = ~b.cpu().numpy()
+    np.testing.assert_array_equal(got[inner], ref[inner])
+    assert np.all(got[~inner] == -5.0)
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (9, 130), (129, 64), (70, 70), (257, 300)])
+@pytest.mark.parametrize("nt", [0, 1, 2, 7, 41])
+def test_run_bitwise(lib, shape, nt):
+    T0, Ci, s = _inputs(shape, seed=nt)
+    T = torch.from_numpy(T0).cuda()
+    lib.run2d(T, torch.empty_like(T), torch.from_numpy(Ci).cuda(), *_sc(s), nt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(T.cpu().numpy(), oracle.forward2d(T0, Ci, *_sc(s), nt))
+
+
+def test_run_4096_bitwise(lib):
+    """A grid of many strips and y-chunks (the launch the benchmark uses at
+    8192^2), compared whole."""
+    shape = (4096, 4096)
+    T0, Ci, s = _inputs(shape, seed=3)
+    T = torch.from_numpy(T0).cuda()
+    lib.run2d(T, torch.empty_like(T), torch.from_numpy(Ci).cuda(), *_sc(s), 10)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(T.cpu().numpy(), oracle.forward2d(T0, Ci, *_sc(s), 10))
+
+
+def test_fp32_against_fp64_oracle(lib):
+    """FP32 storage and arithmetic, 100 steps of a Gaussian bump on 1024^2:
+    max relative error against the FP64 oracle within 1e-5."""
+    n = 1024
+    xs = np.linspace(0.0, 1.0, n)
+    X, Y = np.meshgrid(xs, xs)
+    rng = np.random.default_rng(9)
+    T0 = np.exp(-((X - 0.5) ** 2 + (Y - 0.5) ** 2) / 0.01) + 0.01 * rng.random((n, n))
+    Ci = 0.5 * (1.0 + 0.5 * rng.random((n, n)))
+    s = oracle.scalars2d(n, n, Ci)
+    ref = oracle.forward2d(T0, Ci, *_sc(s), 100)
+    T = torch.from_numpy(T0).to("cuda", torch.float32)
+    lib.run2d(T, torch.empty_like(T), torch.from_numpy(Ci).to("cuda", torch.float32), *_sc(s), 100)
+    torch.cuda.synchronize()
+    rel = np.max(np.abs(T.double().cpu().numpy() - ref) / np.abs(ref))
+    assert rel <= 1e-5, rel
+
+
+def test_rejects_bf16(lib):
+    T = torch.zeros((8, 8), dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(lib.Diff3dError):
+        lib.step2d(torch.empty_like(T), T, T.clone(), 1.0, 1e-4, 7.0, 7.0)
