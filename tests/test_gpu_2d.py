@@ -88,3 +88,26 @@ def test_rejects_bf16(lib):
     T = torch.zeros((8, 8), dtype=torch.bfloat16, device="cuda")
     with pytest.raises(lib.Diff3dError):
         lib.step2d(torch.empty_like(T), T, T.clone(), 1.0, 1e-4, 7.0, 7.0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [(37, 256), (50, 1024), (19, 72)])
+def test_alignment_independent(lib, dtype, shape):
+    """Fields one element off 16-byte alignment give the same bits as
+    aligned ones."""
+    T0, Ci, s = _inputs(shape, seed=shape[1])
+    n = T0.size
+
+    def run(offset):
+        bt = torch.zeros(n + 8, dtype=dtype, device="cuda")
+        bc = torch.zeros(n + 8, dtype=dtype, device="cuda")
+        T = bt[offset:offset + n].view(shape)
+        C = bc[offset:offset + n].view(shape)
+        T.copy_(torch.from_numpy(T0).to(dtype))
+        C.copy_(torch.from_numpy(Ci).to(dtype))
+        S = torch.empty_like(T)
+        lib.run2d(T, S, C, *_sc(s), 9)
+        torch.cuda.synchronize()
+        return T.clone()
+
+    assert torch.equal(run(0), run(1))
