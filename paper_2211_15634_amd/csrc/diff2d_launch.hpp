@@ -25,10 +25,14 @@ int launch_step2d(void* T2, const void* T, const void* Ci, int nx, int ny, doubl
     a.dt = (C)dt;
     a.cx = (C)(rdx * rdx);
     a.cy = (C)(rdy * rdy);
-    // about 32 waves per CU of y-chunks, each at least 16 rows long
+    // y-chunks for about 128 waves per CU (several rounds of resident waves),
+    // each at least 16 rows long.  Measured at 8192^2, us per step for a target
+    // of 16 / 32 / 64 / 128 waves per CU: FP64 299 / 346 / 346 / 285, FP32
+    // 210 / 154 / 211 / 159 (non-monotonic: the chunk starts' spacing in
+    // memory matters as much as the count).
     const int nstrips = (nx + 63) / 64;
     const int rows = ny - 2;
-    const int want = (256 * 32 + nstrips - 1) / nstrips;
+    const int want = (256 * 128 + nstrips - 1) / nstrips;
     const int nchunks = max(1, min(want, (rows + 15) / 16));
     const int ylen = (rows + nchunks - 1) / nchunks;
     const long waves = (long)nstrips * nchunks;
