@@ -34,7 +34,11 @@ int launch_step2d(void* T2, const void* T, const void* Ci, int nx, int ny, doubl
     const int rows = ny - 2;
     const int want = (256 * 128 + nstrips - 1) / nstrips;
     const int nchunks = max(1, min(want, (rows + 15) / 16));
-    const int ylen = (rows + nchunks - 1) / nchunks;
+    // an odd chunk length keeps chunk starts from lying a power of two rows
+    // apart (FP64 at 4096^2: 79 against 101 us per step; FP32 at 8192^2: 148
+    // against 159); chunks past the last row exit at once
+    int ylen = (rows + nchunks - 1) / nchunks;
+    if (ylen > 1) ylen |= 1;
     const long waves = (long)nstrips * nchunks;
     const unsigned blocks = (unsigned)((waves + kStep2dWaves - 1) / kStep2dWaves);
     step2d_ymarch<DT, kStep2dWaves><<<blocks, 64 * kStep2dWaves, 0, st>>>(a, nstrips, nchunks, ylen);
