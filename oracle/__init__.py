@@ -5,8 +5,10 @@ CPU-baseline leg are the only callers.  The product library never imports,
 loads or calls anything here, and this package shares no code with it.
 
 The arithmetic lives in ``diff3d_oracle.c`` (plain triple loops, FP64, no
-fused multiply-add); this module only compiles it with gcc on first use and
-marshals numpy arrays.  ``brute`` holds an exact rational evaluator and a
+fused multiply-add) and ``emulate32.c`` (the same loops in FP32 arithmetic
+with FP32 or BF16 storage, and the Philox4x32-10 generator behind
+stochastic rounding); this module only compiles them with gcc on first use
+and marshals numpy arrays.  ``brute`` holds an exact rational evaluator and a
 dense-matrix evaluator for tiny grids, used to pin the C loops.
 
 Source: Omlin & Raess, "High-performance xPU Stencil Computations in Julia"
@@ -26,6 +28,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "diff3d_oracle.c")
+_SRC32 = os.path.join(_HERE, "emulate32.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -33,10 +36,11 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc (OpenMP, -ffp-contract=off)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC32))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared",
-               "-fPIC", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard", "-fopenmp",
+               "-shared", "-fPIC", "-o", tmp, _SRC, _SRC32, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
@@ -59,6 +63,19 @@ def _load():
             lib.oracle_reverse.restype = i
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = i
+            vp, sz, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64
+            lib.emul_philox4x32_10.argtypes = [vp, vp, vp]
+            lib.emul_philox4x32_10.restype = None
+            lib.emul_sr_bits.argtypes = [u64, u64, vp, vp, sz]
+            lib.emul_sr_bits.restype = None
+            lib.emul_bf16_nearest.argtypes = [vp, vp, sz]
+            lib.emul_bf16_nearest.restype = None
+            lib.emul_bf16_stochastic.argtypes = [vp, vp, vp, sz]
+            lib.emul_bf16_stochastic.restype = None
+            lib.emul_forward.argtypes = [vp, vp, vp, i, i, i, d, d, d, d, d, vp, i, i, u64, u64, i]
+            lib.emul_forward.restype = i
+            lib.emul_reverse32.argtypes = [vp, vp, vp, vp, vp, i, i, i, d, d, d, d, d, i, i, i]
+            lib.emul_reverse32.restype = i
             _lib = lib
     return _lib
 
@@ -155,3 +172,95 @@ def loss_and_seed(T_nt, T_target):
     dL/dT_nt = T_nt - T_target (FP64)."""
     r = _field(T_nt) - _field(T_target)
     return 0.5 * float(np.sum(r * r)), r
+
+
+# ---------------------------------------------------------------- FP32 / BF16
+# Storage codes of the emulator: FP32, BF16 with stochastic rounding, BF16
+# rounded to nearest even.  BF16 fields are numpy uint16 arrays of raw bits.
+ST_F32, ST_BF16_SR, ST_BF16_RNE = 1, 2, 3
+
+
+def _vp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC'11): four 32-bit output words."""
+    c = np.array(ctr, dtype=np.uint32)
+    k = np.array(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    _load().emul_philox4x32_10(_vp(c), _vp(k), _vp(o))
+    return tuple(int(v) for v in o)
+
+
+def sr_bits(seed: int, step: int, idx) -> np.ndarray:
+    """The 16 random bits of the given linear point indices for the state
+    stored after global step index ``step``."""
+    i = np.ascontiguousarray(idx, dtype=np.uint64)
+    out = np.zeros(i.shape, dtype=np.uint16)
+    _load().emul_sr_bits(seed & (2 ** 64 - 1), step & (2 ** 64 - 1), _vp(i), _vp(out), i.size)
+    return out
+
+
+def bf16_nearest(x) -> np.ndarray:
+    """FP32 values -> BF16 bits, round to nearest even."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.zeros(x.shape, dtype=np.uint16)
+    _load().emul_bf16_nearest(_vp(x), _vp(out), x.size)
+    return out
+
+
+def bf16_stochastic(x, r) -> np.ndarray:
+    """FP32 values -> BF16 bits, stochastic rounding with the 16-bit values r."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    r = np.ascontiguousarray(r, dtype=np.uint16)
+    if r.shape != x.shape:
+        raise ValueError("one random value per element")
+    out = np.zeros(x.shape, dtype=np.uint16)
+    _load().emul_bf16_stochastic(_vp(x), _vp(r), _vp(out), x.size)
+    return out
+
+
+def bf16_widen(h) -> np.ndarray:
+    """BF16 bits -> FP32 values (exact)."""
+    h = np.ascontiguousarray(h, dtype=np.uint16)
+    return (h.astype(np.uint32) << 16).view(np.float32)
+
+
+def emulate_forward(T0, Ci, lam: float, dt: float, rdx: float, rdy: float, rdz: float, passes, storage: int,
+                    seed: int = 0, step0: int = 0, threads: int = 0) -> np.ndarray:
+    """The time loop in FP32 arithmetic with the given storage: T0 and Ci are
+    stored values (float32, or uint16 BF16 bits), ``passes`` the pass
+    lengths (states inside a pass stay in FP32; the state at the end of each
+    pass is stored).  Returns the stored final state."""
+    dtype = np.float32 if storage == ST_F32 else np.uint16
+    T0 = np.ascontiguousarray(T0, dtype=dtype)
+    Ci = np.ascontiguousarray(Ci, dtype=dtype)
+    if T0.ndim != 3 or Ci.shape != T0.shape:
+        raise ValueError("fields are two (nz, ny, nx) arrays")
+    nz, ny, nx = T0.shape
+    p = np.ascontiguousarray(passes, dtype=np.int32)
+    T = np.empty_like(T0)
+    rc = _load().emul_forward(_vp(T), _vp(T0), _vp(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _vp(p), p.size,
+                              int(storage), seed & (2 ** 64 - 1), step0 & (2 ** 64 - 1), int(threads))
+    if rc != 0:
+        raise ValueError("emul_forward failed (%d)" % rc)
+    return T
+
+
+def emulate_reverse32(T0, Ci, g_nt, lam: float, dt: float, rdx: float, rdy: float, rdz: float, nt: int,
+                      keep: int = 1, threads: int = 0):
+    """The reverse sweep in FP32 arithmetic and storage: (dLoss/dT0, dLoss/dCi)."""
+    T0 = np.ascontiguousarray(T0, dtype=np.float32)
+    Ci = np.ascontiguousarray(Ci, dtype=np.float32)
+    g = np.ascontiguousarray(g_nt, dtype=np.float32)
+    if T0.ndim != 3 or Ci.shape != T0.shape or g.shape != T0.shape:
+        raise ValueError("fields are three (nz, ny, nx) arrays")
+    nz, ny, nx = T0.shape
+    gT0 = np.empty_like(T0)
+    gCi = np.empty_like(T0)
+    rc = _load().emul_reverse32(_vp(T0), _vp(Ci), _vp(g), _vp(gT0), _vp(gCi), nx, ny, nz, lam, dt, rdx, rdy, rdz,
+                                int(nt), int(keep), int(threads))
+    if rc != 0:
+        raise ValueError("emul_reverse32 failed (%d)" % rc)
+    return gT0, gCi
