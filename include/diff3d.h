@@ -69,11 +69,44 @@ typedef enum {
     DIFF3D_KERNEL_TB2 = 3,     /* diff3d_run: two steps per pass (temporal blocking), z-march
                                   for single steps; bit-identical results */
     DIFF3D_KERNEL_TBS = 4      /* diff3d_run: S steps per pass with the S-step kernel (S from
-                                  diff3d_set_pass_steps), z-march for single steps; diff3d_stepn
+                                  diff3d_config.pass_steps), z-march for single steps; diff3d_stepn
                                   also uses it for two steps; diff3d_adjoint_run: fused reverse
                                   passes of min(S, 3) steps (forward states recomputed on chip);
                                   bit-identical results */
 } diff3d_kernel;
+
+/* Tile configuration override of one kernel family; all zero = the tuned
+ * default.  p[] by family:
+ *   zmarch, tb2 (single-step and two-step kernels): V (points per lane along
+ *       x), R (rows per thread), NW (waves per workgroup), NT (1: Ci loads
+ *       and T2 stores non-temporal);
+ *   adj, adj2 (single-step and two-step adjoint kernels): V, R, NW, unused;
+ *   tbs (S-step kernel): W0, H0 (region), NTH (threads), NT;
+ *   rev (fused reverse passes): W0, H0, NTH, unused.
+ * `steps` names the pass length a tbs or rev override applies to (2 ..
+ * DIFF3D_MAX_PASS_STEPS; other pass lengths keep their defaults); it must be
+ * 0 for the other families.  zlen = planes per z-chunk (0 = automatic).  An
+ * override naming a configuration the library does not instantiate for the
+ * call's dtype is rejected (DIFF3D_EINVAL, nothing enqueued). */
+typedef struct {
+    int steps;
+    int p[4];
+    int zlen;
+} diff3d_tile;
+
+/* Everything that selects how a call runs, owned by the caller and passed to
+ * each call (NULL = all defaults, i.e. a zero-filled struct).  The library
+ * keeps no state between calls: equal arguments give equal bits. */
+typedef struct {
+    int kernel;          /* diff3d_kernel */
+    int pass_steps;      /* under DIFF3D_KERNEL_TBS: steps per pass of diff3d_run, 2 ..
+                            DIFF3D_MAX_PASS_STEPS, or 0 for the dtype's default */
+    int narrow;          /* 1: one point per lane in the z-march, two-step and adjoint kernels */
+    int reserved;        /* must be 0 */
+    uint64_t sr_seed;    /* key of the stochastic rounding of DIFF3D_BF16 */
+    uint64_t sr_step;    /* index of the first time step the call takes (see diff3d_step) */
+    diff3d_tile zmarch, tb2, tbs, adj, adj2, rev;
+} diff3d_config;
 
 /* Largest number of time steps one pass over memory can take (diff3d_stepn). */
 #define DIFF3D_MAX_PASS_STEPS 4
@@ -101,56 +134,93 @@ int diff3d_scalars(int nx, int ny, int nz, double lx, double ly, double lz, doub
  * scratch; the result is deterministic. */
 int diff3d_max(const void* x, size_t n, int dtype, double* acc, void* stream);
 
+/* Reduced-precision storage (DIFF3D_F32, DIFF3D_BF16, DIFF3D_BF16_RNE): loads
+ * widen to FP32, the step is evaluated in FP32 in the order above, and a
+ * value is rounded to the storage type only when a state is written to
+ * memory.  A pass that takes several steps on chip (diff3d_stepn, the time
+ * loop) keeps its intermediate states in FP32, so BF16 results depend on the
+ * pass lengths (diff3d_pass_plan); FP64 and FP32 results do not.
+ * Stochastic rounding (DIFF3D_BF16): the state written after global step
+ * index k (k = cfg->sr_step + the number of steps the call has taken before
+ * that step) draws for point i the 16 random bits r of Philox4x32-10 with key
+ * (sr_seed low word, sr_seed high word) and counter (g low word, g high word,
+ * k low word, k high word), g = i / 8: the low (i even) or high (i odd) half
+ * of output word (i % 8) / 2.  The stored BF16 value is the upper half of
+ * the FP32 bit pattern plus r, truncated to its upper 16 bits (NaN and
+ * infinity kept): it rounds up with probability equal to the discarded
+ * fraction of a BF16 unit in the last place. */
+
 /* One time step (Fig. 1, `step!`).  Writes the interior of T2 from T and Ci;
  * T2's boundary is not touched (the caller keeps it equal to T's, as
- * T2 = copy(T) does in the paper).  T2 must not alias T or Ci.
- * For DIFF3D_BF16 the stochastic rounding draws from the counter
- * (seed, step_index, point), see diff3d_set_sr_seed. */
+ * T2 = copy(T) does in the paper).  T2 must not alias T or Ci.  cfg selects
+ * the kernel (naive or z-march; other values mean z-march) and the
+ * stochastic rounding's seed and step index. */
 int diff3d_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
-                double dt, double rdx, double rdy, double rdz, int dtype, void* stream);
+                double dt, double rdx, double rdy, double rdz, int dtype, void* stream,
+                const diff3d_config* cfg);
 
 /* Two time steps in one pass over memory (temporal blocking): writes the
- * interior of T2 with the state two steps after T, bit-identical to two
- * diff3d_step calls through an intermediate buffer (the intermediate is
- * rounded exactly as storing it would round it; stochastic rounding uses
- * step indices s and s+1 and advances the index by 2).  Same buffer rules
- * as diff3d_step: T2's boundary is not touched, T2 must not alias T or Ci. */
+ * interior of T2 with the state two steps after T; FP64 and FP32 results are
+ * bit-identical to two diff3d_step calls, BF16 keeps the intermediate state
+ * in FP32 and rounds once (step index cfg->sr_step + 1).  Same buffer rules
+ * as diff3d_step. */
 int diff3d_step2(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
-                 double dt, double rdx, double rdy, double rdz, int dtype, void* stream);
+                 double dt, double rdx, double rdy, double rdz, int dtype, void* stream,
+                 const diff3d_config* cfg);
 
 /* nsteps time steps (1 <= nsteps <= DIFF3D_MAX_PASS_STEPS) in one pass over
  * memory (temporal blocking over S = nsteps steps): each workgroup reads its
  * tile of T padded by nsteps points on every side and computes the
  * intermediate states on shrinking regions on chip.  Writes the interior of
- * T2 with the state nsteps steps after T, bit-identical to nsteps diff3d_step
- * calls through intermediate buffers (intermediates are rounded exactly as
- * storing them would round them; stochastic rounding uses step indices
- * s .. s+nsteps-1 and advances the index by nsteps).  nsteps = 1 is
- * diff3d_step; nsteps = 2 runs the kernel of diff3d_step2 except under
- * DIFF3D_KERNEL_TBS (and, under DIFF3D_KERNEL_AUTO, for the BF16 forms).
- * Same buffer rules as diff3d_step; EINVAL for nsteps out of range. */
+ * T2 with the state nsteps steps after T: FP64 and FP32 bit-identical to
+ * nsteps diff3d_step calls; BF16 rounds once, with step index
+ * cfg->sr_step + nsteps - 1.  nsteps = 1 is diff3d_step; nsteps = 2 runs the
+ * kernel of diff3d_step2 except under DIFF3D_KERNEL_TBS (and, under
+ * DIFF3D_KERNEL_AUTO, for the BF16 forms).  Same buffer rules as
+ * diff3d_step; EINVAL for nsteps out of range. */
 int diff3d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
-                 double dt, double rdx, double rdy, double rdz, int nsteps, int dtype, void* stream);
+                 double dt, double rdx, double rdy, double rdz, int nsteps, int dtype, void* stream,
+                 const diff3d_config* cfg);
+
+/* The pass lengths diff3d_run takes for these arguments, in order (host
+ * logic only).  Passes are at most S steps (the kernel's pass length for the
+ * dtype and x-y plane size, or cfg->pass_steps under DIFF3D_KERNEL_TBS); a
+ * pass never crosses a checkpointed state (a multiple of ckpt_every below
+ * nt; ckpt_every = 0: no checkpoints); with the default pass length each
+ * stretch between checkpoints is split into passes of near-equal length
+ * (14 steps at S = 4: 4, 4, 3, 3), with a set pass length into passes of
+ * exactly that length and a shorter last one.  Returns the number of passes
+ * (writing at most max_lengths of them to lengths, which may be NULL), or a
+ * negative diff3d_status. */
+int diff3d_pass_plan(int nx, int ny, int nz, int nt, int ckpt_every, int dtype,
+                     const diff3d_config* cfg, int* lengths, int max_lengths);
 
 /* nt time steps with the buffer swap of Fig. 1.  First copies T's boundary
- * into T2, then alternates passes (of one or more steps) T -> T2 -> T ...
- * The result T_nt is always left in T (one extra copy when the last pass
- * ends in T2); T2 is scratch.
+ * into T2, then runs the passes of diff3d_pass_plan, alternating
+ * T -> T2 -> T ...  The result T_nt is always left in T (one extra copy when
+ * the last pass ends in T2); T2 is scratch.
  * Checkpoints: if ckpt is not NULL, the states T_{j*C} for j = 1 .. nck-1,
  * C = ckpt_every, nck = ceil(nt/C), are stored in consecutive fields of ckpt
- * (field j-1 holds T_{j*C}, boundary included): the pass that reaches such a
- * state writes it there; this is the first part of the workspace of
- * diff3d_adjoint_run, which can then be called with ckpt_ready = 1.
- * ckpt_every must be >= 1 when ckpt is given.  nt = 0 leaves T unchanged. */
+ * (field j-1 holds T_{j*C}, boundary included, each field rounded up to a
+ * multiple of 256 bytes): the pass that reaches such a state writes it
+ * there; this is the first part of the workspace of diff3d_adjoint_run,
+ * which can then be called with ckpt_ready = 1.  ckpt_every must be >= 1
+ * when ckpt is given.  nt = 0 leaves T unchanged.  Stochastic rounding uses
+ * step indices cfg->sr_step .. cfg->sr_step + nt - 1. */
 int diff3d_run(void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt,
                double rdx, double rdy, double rdz, int nt, int dtype, void* stream, void* ckpt,
-               int ckpt_every);
+               int ckpt_every, const diff3d_config* cfg);
 
-/* Bytes of workspace for diff3d_adjoint_run: (nck - 1) checkpoint fields,
- * (C - 1) fields for the states recomputed inside a segment and one field
- * for the adjoint ping-pong, each nx*ny*nz*sizeof(dtype), rounded up to
- * 256-byte field boundaries.  Returns 0 for invalid arguments. */
-size_t diff3d_adjoint_workspace_bytes(int nx, int ny, int nz, int nt, int ckpt_every, int dtype);
+/* Bytes of workspace for diff3d_adjoint_run with the same cfg: (nck - 1)
+ * checkpoint fields, the fields for states recomputed inside a checkpoint
+ * segment, and one field for the adjoint ping-pong, each
+ * nx*ny*nz*sizeof(dtype) rounded up to a multiple of 256 bytes.  The
+ * recomputed states are those at the starts of the fused reverse passes
+ * (DIFF3D_KERNEL_AUTO, DIFF3D_KERNEL_TBS: ceil(L/P) - 1 fields, L =
+ * min(ckpt_every, nt), P the fused pass length) or every state of a segment
+ * (the other kernels: L - 1 fields).  Returns 0 for invalid arguments. */
+size_t diff3d_adjoint_workspace_bytes(int nx, int ny, int nz, int nt, int ckpt_every, int dtype,
+                                      const diff3d_config* cfg);
 
 /* Reverse sweep of nt steps (the transpose of the step, derived by hand):
  * given gTnt = dLoss/dT_nt, writes gT0 = dLoss/dT0 and overwrites gCi with
@@ -168,11 +238,12 @@ size_t diff3d_adjoint_workspace_bytes(int nx, int ny, int nz, int nt, int ckpt_e
  * already holds them from diff3d_run with the same T0, Ci, scalars, nt,
  * ckpt_every and dtype).  Only DIFF3D_F64 and DIFF3D_F32 are supported
  * (EDTYPE otherwise).  gT0, gCi and the workspace must not overlap each
- * other or the inputs. */
+ * other or the inputs; ws_bytes must be at least
+ * diff3d_adjoint_workspace_bytes(..., cfg). */
 int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* gT0, void* gCi,
                        void* workspace, size_t ws_bytes, int ckpt_ready, int nx, int ny, int nz,
                        double lam, double dt, double rdx, double rdy, double rdz, int nt,
-                       int ckpt_every, int dtype, void* stream);
+                       int ckpt_every, int dtype, void* stream, const diff3d_config* cfg);
 
 /* Loss of the gradient examples: L = 0.5*sum((T - Tt)^2) over all n points,
  * accumulated in FP64 into acc[0] (acc: DIFF3D_REDUCE_DOUBLES doubles of
@@ -189,21 +260,6 @@ int diff3d_norm2(const void* x, size_t n, int dtype, double* acc, void* stream);
  * measured copy bandwidth is the reachable-peak reference).  dst and src
  * must not overlap and must be 16-byte aligned. */
 int diff3d_copy(void* dst, const void* src, size_t bytes, void* stream);
-
-/* Process-wide settings (not thread safe; they apply to later calls). */
-/* Select the forward step variant (diff3d_kernel); EINVAL if unknown. */
-int diff3d_set_kernel(int kernel);
-int diff3d_get_kernel(void);
-/* Steps per pass of diff3d_run under DIFF3D_KERNEL_TBS: 2 .. DIFF3D_MAX_PASS_STEPS,
- * or 0 for the default of each dtype; EINVAL otherwise (1 is DIFF3D_KERNEL_ZMARCH).
- * A set length gives passes of exactly that many steps, shortened only at a
- * checkpoint or the end; the default splits each stretch between checkpoints
- * into passes of near-equal length. */
-int diff3d_set_pass_steps(int nsteps);
-/* Seed of the stochastic rounding of DIFF3D_BF16 and the step index the
- * next diff3d_step uses; diff3d_run uses indices step0 .. step0+nt-1 and
- * advances the index by nt, diff3d_step by 1. */
-void diff3d_set_sr_seed(uint64_t seed, uint64_t step0);
 
 /* The 2-D form of the step (not printed in the paper, whose Fig. 1 is the
  * 3-D solver): the Fig. 1 expression without the z term,

@@ -16,6 +16,7 @@ paper's column-major Julia arrays).
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import os
 
 import torch
@@ -38,6 +39,21 @@ REDUCE_DOUBLES = 1025
 _vp, _i, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
 _dp = ctypes.POINTER(ctypes.c_double)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class _CTile(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("p", ctypes.c_int * 4), ("zlen", ctypes.c_int)]
+
+
+class _CConfig(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int), ("pass_steps", ctypes.c_int), ("narrow", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("sr_seed", ctypes.c_uint64), ("sr_step", ctypes.c_uint64),
+                ("zmarch", _CTile), ("tb2", _CTile), ("tbs", _CTile), ("adj", _CTile), ("adj2", _CTile),
+                ("rev", _CTile)]
+
+
+_cfgp = ctypes.POINTER(_CConfig)
 
 _SIGS = {
     "diff3d_strerror": ([_i], ctypes.c_char_p),
@@ -45,20 +61,17 @@ _SIGS = {
     "diff3d_version": ([], ctypes.c_char_p),
     "diff3d_scalars": ([_i, _i, _i, _d, _d, _d, _d, _d, _dp], _i),
     "diff3d_max": ([_vp, _sz, _i, _vp, _vp], _i),
-    "diff3d_step": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _vp], _i),
-    "diff3d_step2": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _vp], _i),
-    "diff3d_stepn": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _vp], _i),
-    "diff3d_run": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _vp, _vp, _i], _i),
-    "diff3d_adjoint_workspace_bytes": ([_i, _i, _i, _i, _i, _i], _sz),
+    "diff3d_step": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _vp, _cfgp], _i),
+    "diff3d_step2": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _vp, _cfgp], _i),
+    "diff3d_stepn": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _vp, _cfgp], _i),
+    "diff3d_pass_plan": ([_i, _i, _i, _i, _i, _i, _cfgp, _ip, _i], _i),
+    "diff3d_run": ([_vp, _vp, _vp, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _vp, _vp, _i, _cfgp], _i),
+    "diff3d_adjoint_workspace_bytes": ([_i, _i, _i, _i, _i, _i, _cfgp], _sz),
     "diff3d_adjoint_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _i, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _i,
-                            _vp], _i),
+                            _vp, _cfgp], _i),
     "diff3d_loss": ([_vp, _vp, _vp, _sz, _i, _vp, _vp], _i),
     "diff3d_norm2": ([_vp, _sz, _i, _vp, _vp], _i),
     "diff3d_copy": ([_vp, _vp, _sz, _vp], _i),
-    "diff3d_set_kernel": ([_i], _i),
-    "diff3d_get_kernel": ([], _i),
-    "diff3d_set_pass_steps": ([_i], _i),
-    "diff3d_set_sr_seed": ([ctypes.c_uint64, ctypes.c_uint64], None),
     "diff3d_philox4x32_10": ([_u32p, _u32p, _u32p], None),
     "diff2d_step": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _vp], _i),
     "diff2d_run": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _vp], _i),
@@ -69,6 +82,61 @@ for _name, (_args, _res) in _SIGS.items():
     _f.restype = _res
 
 EXPORTS = tuple(_SIGS)
+
+
+@dataclasses.dataclass(frozen=True)
+class Tile:
+    """Tile override of one kernel family (diff3d_tile): ``p`` holds
+    (V, R, NW, NT) for the z-march and two-step kernels, (V, R, NW, 0) for
+    the adjoint kernels, (W0, H0, NTH, NT) for the S-step kernel and
+    (W0, H0, NTH, 0) for fused reverse passes; ``steps`` is the pass length
+    an S-step or reverse override applies to; ``zlen`` the planes per
+    z-chunk (0 = automatic).  All zero = the tuned default."""
+    steps: int = 0
+    p: tuple = (0, 0, 0, 0)
+    zlen: int = 0
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    """Per-call configuration (diff3d_config): kernel choice, pass length,
+    stochastic-rounding seed and first step index, tile overrides.  The
+    library keeps no state between calls; the default is a zero-filled
+    struct."""
+    kernel: int = 0
+    pass_steps: int = 0
+    narrow: bool = False
+    sr_seed: int = 0
+    sr_step: int = 0
+    zmarch: Tile = Tile()
+    tb2: Tile = Tile()
+    tbs: Tile = Tile()
+    adj: Tile = Tile()
+    adj2: Tile = Tile()
+    rev: Tile = Tile()
+
+    def replace(self, **kw) -> "Config":
+        return dataclasses.replace(self, **kw)
+
+
+def _ctile(t: Tile) -> _CTile:
+    p = tuple(int(v) for v in t.p) + (0,) * (4 - len(t.p))
+    return _CTile(int(t.steps), (ctypes.c_int * 4)(*p[:4]), int(t.zlen))
+
+
+def _ccfg(cfg: Config | None):
+    if cfg is None:
+        return None
+    c = _CConfig()
+    c.kernel = int(cfg.kernel)
+    c.pass_steps = int(cfg.pass_steps)
+    c.narrow = int(bool(cfg.narrow))
+    c.reserved = 0
+    c.sr_seed = int(cfg.sr_seed) & (2 ** 64 - 1)
+    c.sr_step = int(cfg.sr_step) & (2 ** 64 - 1)
+    for name in ("zmarch", "tb2", "tbs", "adj", "adj2", "rev"):
+        setattr(c, name, _ctile(getattr(cfg, name)))
+    return ctypes.byref(c)
 
 
 class Diff3dError(RuntimeError):
@@ -122,23 +190,6 @@ def version() -> str:
 
 def strerror(status: int) -> str:
     return _lib.diff3d_strerror(status).decode()
-
-
-def set_kernel(kind: int) -> None:
-    _check(_lib.diff3d_set_kernel(kind), "set_kernel")
-
-
-def get_kernel() -> int:
-    return _lib.diff3d_get_kernel()
-
-
-def set_pass_steps(nsteps: int) -> None:
-    """Steps per pass of run() under KERNEL_TBS (0 = the dtype's default)."""
-    _check(_lib.diff3d_set_pass_steps(int(nsteps)), "set_pass_steps")
-
-
-def set_sr_seed(seed: int, step0: int = 0) -> None:
-    _lib.diff3d_set_sr_seed(seed & (2 ** 64 - 1), step0 & (2 ** 64 - 1))
 
 
 def philox4x32_10(ctr, key):
@@ -216,7 +267,7 @@ def run2d(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: f
 
 
 def step(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
-         rdz: float, rounding: str = "sr") -> None:
+         rdz: float, rounding: str = "sr", cfg: Config | None = None) -> None:
     """One step: interior of T2 from T and Ci (T2's boundary untouched)."""
     _field(T, "T")
     _field(T2, "T2", T)
@@ -224,11 +275,11 @@ def step(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: fl
     nz, ny, nx = T.shape
     with _on(T):
         _check(_lib.diff3d_step(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _code(T, rounding),
-                                _stream(T)), "step")
+                                _stream(T), _ccfg(cfg)), "step")
 
 
 def step2(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
-          rdz: float, rounding: str = "sr") -> None:
+          rdz: float, rounding: str = "sr", cfg: Config | None = None) -> None:
     """Two steps in one pass: interior of T2 = state two steps after T."""
     _field(T, "T")
     _field(T2, "T2", T)
@@ -236,11 +287,11 @@ def step2(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: f
     nz, ny, nx = T.shape
     with _on(T):
         _check(_lib.diff3d_step2(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _code(T, rounding),
-                                 _stream(T)), "step2")
+                                 _stream(T), _ccfg(cfg)), "step2")
 
 
 def stepn(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
-          rdz: float, nsteps: int, rounding: str = "sr") -> None:
+          rdz: float, nsteps: int, rounding: str = "sr", cfg: Config | None = None) -> None:
     """nsteps steps in one pass: interior of T2 = state nsteps steps after T."""
     _field(T, "T")
     _field(T2, "T2", T)
@@ -248,11 +299,26 @@ def stepn(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: f
     nz, ny, nx = T.shape
     with _on(T):
         _check(_lib.diff3d_stepn(_p(T2), _p(T), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nsteps),
-                                 _code(T, rounding), _stream(T)), "stepn")
+                                 _code(T, rounding), _stream(T), _ccfg(cfg)), "stepn")
+
+
+def pass_plan(shape, nt: int, dtype: torch.dtype, ckpt_every: int = 0, rounding: str = "sr",
+              cfg: Config | None = None) -> list:
+    """The pass lengths run() takes for these arguments (host logic of the
+    library, no GPU work)."""
+    nz, ny, nx = shape
+    code = {torch.float64: F64, torch.float32: F32}.get(dtype, BF16 if rounding == "sr" else BF16_RNE)
+    n = _lib.diff3d_pass_plan(nx, ny, nz, int(nt), int(ckpt_every), code, _ccfg(cfg), None, 0)
+    if n < 0:
+        raise Diff3dError(n, "pass_plan")
+    out = (ctypes.c_int * max(n, 1))()
+    _lib.diff3d_pass_plan(nx, ny, nz, int(nt), int(ckpt_every), code, _ccfg(cfg), out, n)
+    return list(out[:n])
 
 
 def run(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
-        rdz: float, nt: int, rounding: str = "sr", ckpt: torch.Tensor | None = None, ckpt_every: int = 0) -> None:
+        rdz: float, nt: int, rounding: str = "sr", ckpt: torch.Tensor | None = None, ckpt_every: int = 0,
+        cfg: Config | None = None) -> None:
     """nt steps with the swap; the result is left in T (T2 is scratch).
     ``ckpt`` (a uint8 device buffer, e.g. an adjoint workspace) receives
     T_{j*ckpt_every} for j >= 1."""
@@ -261,8 +327,9 @@ def run(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: flo
     _field(Ci, "Ci", T)
     nz, ny, nx = T.shape
     if ckpt is not None:
-        if not ckpt.is_cuda or not ckpt.is_contiguous():
-            raise ValueError("ckpt must be a contiguous GPU buffer")
+        if not isinstance(ckpt, torch.Tensor) or not ckpt.is_cuda or not ckpt.is_contiguous() or \
+                ckpt.device != T.device:
+            raise ValueError("ckpt must be a contiguous GPU buffer on T's device")
         if ckpt_every < 1:
             raise ValueError("ckpt_every must be >= 1 with a checkpoint buffer")
         nck = (nt + ckpt_every - 1) // ckpt_every if nt > 0 else 0
@@ -271,27 +338,32 @@ def run(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: flo
             raise ValueError("ckpt buffer too small for %d checkpoints" % max(nck - 1, 0))
     with _on(T):
         _check(_lib.diff3d_run(_p(T), _p(T2), _p(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nt), _code(T, rounding),
-                               _stream(T), _p(ckpt), int(ckpt_every)), "run")
+                               _stream(T), _p(ckpt), int(ckpt_every), _ccfg(cfg)), "run")
 
 
-def adjoint_workspace_bytes(shape, nt: int, ckpt_every: int, dtype: torch.dtype) -> int:
+def adjoint_workspace_bytes(shape, nt: int, ckpt_every: int, dtype: torch.dtype, cfg: Config | None = None) -> int:
     nz, ny, nx = shape
     code = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[dtype]
-    return int(_lib.diff3d_adjoint_workspace_bytes(nx, ny, nz, int(nt), int(ckpt_every), code))
+    return int(_lib.diff3d_adjoint_workspace_bytes(nx, ny, nz, int(nt), int(ckpt_every), code, _ccfg(cfg)))
 
 
 def adjoint_run(T0, Ci, gTnt, gT0, gCi, workspace, ckpt_ready: bool, lam, dt, rdx, rdy, rdz, nt: int,
-                ckpt_every: int) -> None:
-    """Reverse sweep: gT0 = dL/dT0 and gCi = dL/dCi from gTnt = dL/dT_nt."""
+                ckpt_every: int, cfg: Config | None = None) -> None:
+    """Reverse sweep: gT0 = dL/dT0 and gCi = dL/dCi from gTnt = dL/dT_nt.
+    ``workspace`` is a contiguous device buffer on T0's device of at least
+    adjoint_workspace_bytes(..., cfg) bytes."""
     _field(T0, "T0")
     for name, t in (("Ci", Ci), ("gTnt", gTnt), ("gT0", gT0), ("gCi", gCi)):
         _field(t, name, T0)
+    if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or not workspace.is_contiguous() or \
+            workspace.device != T0.device:
+        raise ValueError("workspace must be a contiguous GPU buffer on T0's device")
     nz, ny, nx = T0.shape
     with _on(T0):
         _check(_lib.diff3d_adjoint_run(_p(T0), _p(Ci), _p(gTnt), _p(gT0), _p(gCi), _p(workspace),
-                                       workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                       workspace.numel() * workspace.element_size(),
                                        int(bool(ckpt_ready)), nx, ny, nz, lam, dt, rdx, rdy, rdz, int(nt),
-                                       int(ckpt_every), _code(T0), _stream(T0)), "adjoint_run")
+                                       int(ckpt_every), _code(T0), _stream(T0), _ccfg(cfg)), "adjoint_run")
 
 
 def loss(T: torch.Tensor, Tt: torch.Tensor, seed: torch.Tensor | None = None) -> torch.Tensor:
@@ -318,7 +390,13 @@ def norm2(x: torch.Tensor) -> torch.Tensor:
 
 
 def copy_(dst: torch.Tensor, src: torch.Tensor) -> None:
-    """Device copy through the library's streaming copy kernel."""
+    """Device copy through the library's streaming copy kernel (contiguous
+    GPU tensors on one device)."""
+    for name, t in (("dst", dst), ("src", src)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous GPU tensor" % name)
+    if dst.device != src.device:
+        raise ValueError("dst and src must be on one device")
     nbytes = src.numel() * src.element_size()
     if dst.numel() * dst.element_size() < nbytes:
         raise ValueError("dst too small")
@@ -332,18 +410,19 @@ class Diffuse3D(torch.autograd.Function):
     every ``ckpt_every`` steps, recomputation in between)."""
 
     @staticmethod
-    def forward(ctx, T0, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt_every):
+    def forward(ctx, T0, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt_every, cfg=None):
         if T0.dtype not in (torch.float64, torch.float32):
             raise TypeError("gradients are supported for float64 and float32 fields")
         T0 = T0.contiguous()
         Ci = Ci.contiguous()
         T = T0.clone()
         T2 = torch.empty_like(T0)
-        ws_bytes = adjoint_workspace_bytes(T0.shape, nt, ckpt_every, T0.dtype)
+        ws_bytes = adjoint_workspace_bytes(T0.shape, nt, ckpt_every, T0.dtype, cfg)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=T0.device)
-        run(T, T2, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt=ws, ckpt_every=ckpt_every)
+        run(T, T2, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt=ws, ckpt_every=ckpt_every, cfg=cfg)
         ctx.save_for_backward(T0, Ci)
         ctx.ws = ws
+        ctx.cfg = cfg
         ctx.args = (lam, dt, rdx, rdy, rdz, int(nt), int(ckpt_every))
         return T
 
@@ -354,13 +433,13 @@ class Diffuse3D(torch.autograd.Function):
         gT = gT.contiguous()
         gT0 = torch.empty_like(T0)
         gCi = torch.empty_like(Ci)
-        adjoint_run(T0, Ci, gT, gT0, gCi, ctx.ws, True, lam, dt, rdx, rdy, rdz, nt, ce)
+        adjoint_run(T0, Ci, gT, gT0, gCi, ctx.ws, True, lam, dt, rdx, rdy, rdz, nt, ce, cfg=ctx.cfg)
         ctx.ws = None
-        return gT0, gCi, None, None, None, None, None, None, None
+        return gT0, gCi, None, None, None, None, None, None, None, None
 
 
-def diffuse(T0, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt_every=None):
+def diffuse(T0, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt_every=None, cfg: Config | None = None):
     """Differentiable nt-step diffusion; ckpt_every defaults to about sqrt(nt)."""
     if ckpt_every is None:
         ckpt_every = max(1, int(round(nt ** 0.5)))
-    return Diffuse3D.apply(T0, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt_every)
+    return Diffuse3D.apply(T0, Ci, lam, dt, rdx, rdy, rdz, nt, ckpt_every, cfg)

@@ -51,21 +51,20 @@ int launch_adj_cfg(const AdjArgs<DT>& a, hipStream_t st, int zlen_req, int zdef)
 
 template <int DT>
 int launch_adj(void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny, int nz,
-               double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+               double lam, double dt, double rdx, double rdy, double rdz, const diff3d_config& c, hipStream_t st)
 {
     using S = typename Traits<DT>::S;
     const AdjArgs<DT> a = make_adj_args<DT>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz);
-    if (g_kernel == DIFF3D_KERNEL_NAIVE) {
+    if (c.kernel == DIFF3D_KERNEL_NAIVE) {
         dim3 grid((unsigned)((nx + 63) / 64), (unsigned)((ny + 3) / 4), (unsigned)min(nz, 65535));
         adj_naive<DT><<<grid, 256, 0, st>>>(a);
         return hip_status();
     }
-    ZKey k = AdjDefaults<DT>::wide;
-    env_key("DIFF3D_ACFG", k);
+    ZKey k = zkey_of(c.adj, AdjDefaults<DT>::wide);
     const bool aligned = (uintptr_t)lout % 16 == 0 && (uintptr_t)lin % 16 == 0 && (uintptr_t)Ci % 16 == 0 &&
                          (uintptr_t)Tk % 16 == 0 && (uintptr_t)gCi % 16 == 0;
-    if (k.V > 1 && (env_int("DIFF3D_NARROW", 0) || nx % k.V != 0 || !aligned)) k = kNarrow;
-    const int zlen = env_int("DIFF3D_AZLEN", 0);
+    if (k.V > 1 && (c.narrow || nx % k.V != 0 || !aligned)) k = kNarrow;
+    const int zlen = c.adj.zlen;
     const int zdef = AdjDefaults<DT>::zdef;
 #define DIFF3D_TRY(v, r, nw) \
     if (k.V == v && k.R == r && k.NW == nw) return launch_adj_cfg<DT, v, r, nw>(a, st, zlen, zdef);
@@ -100,17 +99,17 @@ int launch_adj2_cfg(const AdjArgs<DT>& a, hipStream_t st, int zlen_req, int zdef
 
 template <int DT>
 int launch_adj2(void* lout, const void* lin, const void* Ci, const void* Tk, const void* Tk1, void* gCi, int nx,
-                int ny, int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+                int ny, int nz, double lam, double dt, double rdx, double rdy, double rdz, const diff3d_config& c,
+                hipStream_t st)
 {
     using S = typename Traits<DT>::S;
     AdjArgs<DT> a = make_adj_args<DT>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz);
     a.Tk1 = static_cast<const S*>(Tk1);
-    ZKey k = Adj2Defaults<DT>::wide;
-    env_key("DIFF3D_BCFG", k);
+    ZKey k = zkey_of(c.adj2, Adj2Defaults<DT>::wide);
     const bool aligned = (uintptr_t)lout % 16 == 0 && (uintptr_t)lin % 16 == 0 && (uintptr_t)Ci % 16 == 0 &&
                          (uintptr_t)Tk % 16 == 0 && (uintptr_t)Tk1 % 16 == 0 && (uintptr_t)gCi % 16 == 0;
-    if (k.V > 1 && (env_int("DIFF3D_NARROW", 0) || nx % k.V != 0 || !aligned)) k = kNarrowAdj2;
-    const int zlen = env_int("DIFF3D_BZLEN", 0);
+    if (k.V > 1 && (c.narrow || nx % k.V != 0 || !aligned)) k = kNarrowAdj2;
+    const int zlen = c.adj2.zlen;
     const int zdef = Adj2Defaults<DT>::zdef;
 #define DIFF3D_TRY(v, r, nw) \
     if (k.V == v && k.R == r && k.NW == nw) return launch_adj2_cfg<DT, v, r, nw>(a, st, zlen, zdef);
@@ -124,13 +123,14 @@ int launch_adj2(void* lout, const void* lin, const void* Ci, const void* Tk, con
 }
 
 int adj2_dispatch(int dtype, void* lout, const void* lin, const void* Ci, const void* Tk, const void* Tk1, void* gCi,
-                  int nx, int ny, int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+                  int nx, int ny, int nz, double lam, double dt, double rdx, double rdy, double rdz,
+                  const diff3d_config& c, hipStream_t st)
 {
     switch (dtype) {
     case DIFF3D_F64:
-        return launch_adj2<DIFF3D_F64>(lout, lin, Ci, Tk, Tk1, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+        return launch_adj2<DIFF3D_F64>(lout, lin, Ci, Tk, Tk1, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
     case DIFF3D_F32:
-        return launch_adj2<DIFF3D_F32>(lout, lin, Ci, Tk, Tk1, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+        return launch_adj2<DIFF3D_F32>(lout, lin, Ci, Tk, Tk1, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
     default: return DIFF3D_EDTYPE;
     }
 }
@@ -175,7 +175,8 @@ int launch_rev_cfg(const RevArgs<DT>& a, hipStream_t st, int zlen_req)
 // S reverse steps lambda_{k+S} -> lambda_k from the state T_k (2 <= S <= kMaxRevSteps).
 template <int DT>
 int launch_rev(int nsteps, void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny,
-               int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+               int nz, double lam, double dt, double rdx, double rdy, double rdz, const diff3d_config& c,
+               hipStream_t st)
 {
     using Sz = typename Traits<DT>::S;
     using C = typename Traits<DT>::C;
@@ -196,14 +197,8 @@ int launch_rev(int nsteps, void* lout, const void* lin, const void* Ci, const vo
     a.cy = (C)(rdy * rdy);
     a.cz = (C)(rdz * rdz);
     RKey k = RevDefaults<DT>::key[nsteps];
-    {
-        // tuning override "S,W0,H0,NTH" for passes of S steps
-        const char* e = getenv("DIFF3D_RCFG");
-        int es = 0;
-        RKey r{0, 0, 0};
-        if (e && *e && sscanf(e, "%d,%d,%d,%d", &es, &r.W0, &r.H0, &r.NTH) == 4 && es == nsteps) k = r;
-    }
-    const int zlen = env_int("DIFF3D_RZLEN", 0);
+    if (tile_set(c.rev) && c.rev.steps == nsteps) k = RKey{c.rev.p[0], c.rev.p[1], c.rev.p[2]};
+    const int zlen = szlen_of(c.rev, nsteps);
 #define DIFF3D_TRY(s, w0, h0, nth) \
     if (nsteps == s && k.W0 == w0 && k.H0 == h0 && k.NTH == nth) return launch_rev_cfg<DT, s, w0, h0, nth>(a, st, zlen);
     if constexpr (sizeof(Sz) == 8) {
@@ -216,34 +211,108 @@ int launch_rev(int nsteps, void* lout, const void* lin, const void* Ci, const vo
 }
 
 int rev_dispatch(int dtype, int nsteps, void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx,
-                 int ny, int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+                 int ny, int nz, double lam, double dt, double rdx, double rdy, double rdz, const diff3d_config& c,
+                 hipStream_t st)
 {
     switch (dtype) {
     case DIFF3D_F64:
-        return launch_rev<DIFF3D_F64>(nsteps, lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+        return launch_rev<DIFF3D_F64>(nsteps, lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
     case DIFF3D_F32:
-        return launch_rev<DIFF3D_F32>(nsteps, lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+        return launch_rev<DIFF3D_F32>(nsteps, lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
     default: return DIFF3D_EDTYPE;
     }
 }
 
 // Steps per fused reverse pass: the dtype's default, or the S-step pass
 // length when set (capped at kMaxRevSteps).
-int rev_pass_steps(int dtype)
+int rev_pass_steps(int dtype, const diff3d_config& c)
 {
     const int d = dtype == DIFF3D_F64 ? RevDefaults<DIFF3D_F64>::S : RevDefaults<DIFF3D_F32>::S;
-    if (g_kernel == DIFF3D_KERNEL_TBS && g_pass_steps >= 2) return min(g_pass_steps, kMaxRevSteps);
+    if (c.kernel == DIFF3D_KERNEL_TBS && c.pass_steps >= 2) return min(c.pass_steps, kMaxRevSteps);
     return d;
 }
 
+// The reverse sweep runs fused passes under AUTO and TBS, and recomputes
+// every state of a segment otherwise.
+inline bool rev_fused(const diff3d_config& c)
+{
+    return c.kernel == DIFF3D_KERNEL_TBS || c.kernel == DIFF3D_KERNEL_AUTO;
+}
+
+// Fields for the states recomputed inside one checkpoint segment of at most
+// L = min(C, nt) steps: the starts of the fused passes after the first
+// (ceil(L/P) - 1), or every state after the segment's first (L - 1).
+inline int recompute_fields(int dtype, int nt, int C, const diff3d_config& c)
+{
+    const int L = min(C, nt);
+    if (L <= 1) return 0;
+    if (rev_fused(c)) {
+        const int P = rev_pass_steps(dtype, c);
+        return (L + P - 1) / P - 1;
+    }
+    return L - 1;
+}
+
 int adj_dispatch(int dtype, void* lout, const void* lin, const void* Ci, const void* Tk, void* gCi, int nx, int ny,
-                 int nz, double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+                 int nz, double lam, double dt, double rdx, double rdy, double rdz, const diff3d_config& c,
+                 hipStream_t st)
 {
     switch (dtype) {
-    case DIFF3D_F64: return launch_adj<DIFF3D_F64>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
-    case DIFF3D_F32: return launch_adj<DIFF3D_F32>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    case DIFF3D_F64:
+        return launch_adj<DIFF3D_F64>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
+    case DIFF3D_F32:
+        return launch_adj<DIFF3D_F32>(lout, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
     default: return DIFF3D_EDTYPE;
     }
+}
+
+inline bool adj_has(int size, const ZKey& k)
+{
+#define DIFF3D_HAS(v, r, nw) || (k.V == v && k.R == r && k.NW == nw && k.NT == 0)
+    switch (size) {
+    case 8: return false DIFF3D_ADJ_CFGS_8(DIFF3D_HAS);
+    case 4: return false DIFF3D_ADJ_CFGS_4(DIFF3D_HAS);
+    default: return false;
+    }
+#undef DIFF3D_HAS
+}
+
+inline bool adj2_has(int size, const ZKey& k)
+{
+#define DIFF3D_HAS(v, r, nw) || (k.V == v && k.R == r && k.NW == nw && k.NT == 0)
+    switch (size) {
+    case 8: return false DIFF3D_ADJ2_CFGS_8(DIFF3D_HAS);
+    case 4: return false DIFF3D_ADJ2_CFGS_4(DIFF3D_HAS);
+    default: return false;
+    }
+#undef DIFF3D_HAS
+}
+
+inline bool rev_has(int size, int S, const RKey& k)
+{
+#define DIFF3D_HAS(s, w0, h0, nth) || (S == s && k.W0 == w0 && k.H0 == h0 && k.NTH == nth)
+    switch (size) {
+    case 8: return false DIFF3D_REV_CFGS_8(DIFF3D_HAS);
+    case 4: return false DIFF3D_REV_CFGS_4(DIFF3D_HAS);
+    default: return false;
+    }
+#undef DIFF3D_HAS
+}
+
+// Validation of the reverse sweep's configuration (the forward part is
+// checked by check_forward_config).
+int check_adjoint_config(const diff3d_config& c, int dtype)
+{
+    const int size = (int)elem_size(dtype);
+    if (c.adj.steps != 0 || c.adj2.steps != 0 || c.adj.zlen < 0 || c.adj2.zlen < 0 || c.rev.zlen < 0)
+        return DIFF3D_EINVAL;
+    if (tile_set(c.adj) && !adj_has(size, zkey_of(c.adj, kNarrow))) return DIFF3D_EINVAL;
+    if (tile_set(c.adj2) && !adj2_has(size, zkey_of(c.adj2, kNarrow))) return DIFF3D_EINVAL;
+    if (c.rev.steps != 0 && (c.rev.steps < 2 || c.rev.steps > kMaxRevSteps)) return DIFF3D_EINVAL;
+    if (tile_set(c.rev) &&
+        (c.rev.steps == 0 || c.rev.p[3] != 0 || !rev_has(size, c.rev.steps, RKey{c.rev.p[0], c.rev.p[1], c.rev.p[2]})))
+        return DIFF3D_EINVAL;
+    return DIFF3D_OK;
 }
 
 }  // namespace

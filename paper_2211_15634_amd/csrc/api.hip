@@ -25,28 +25,14 @@ namespace {
 // state is left in T.
 int run_loop(int dtype, void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
              double rdy, double rdz, int nt, hipStream_t st, void* ckpt, int C, size_t field_stride, int klast,
-             bool want_result)
+             bool want_result, const diff3d_config& c)
 {
     int rc = boundary_dispatch(dtype, T2, T, nx, ny, nz, st);
     if (rc) return rc;
     const size_t fbytes = npoints(nx, ny, nz) * elem_size(dtype);
     void* cur = T;                                // holds the current state
-    const int P = run_pass_steps(dtype, nx, ny);
-    // a pass length set with diff3d_set_pass_steps is kept (P, P, .., rest)
-    const bool even = !(g_kernel == DIFF3D_KERNEL_TBS && g_pass_steps);
-    for (int it = 0; it < nt;) {
-        // Passes of at most P steps.  With the default pass length the
-        // stretch up to the next checkpointed state (or to nt) is split into
-        // passes of near-equal length: 14 steps with P = 4 as 4, 4, 3, 3
-        // rather than 4, 4, 4, 2 (short passes cost more per step).
-        int end = nt;
-        if (ckpt) {
-            const int next = (it / C + 1) * C;   // next checkpointed step
-            if (next <= klast && next < end) end = next;
-        }
-        const int rem = end - it;
-        const int m = (rem + P - 1) / P;
-        const int n = even ? (rem + m - 1) / m : min(P, rem);
+    for_each_pass(dtype, nx, ny, nt, ckpt ? C : 0, klast, c, [&](int it, int n) {
+        if (rc) return;
         const int k = it + n;
         // a pass ending on a checkpointed state writes it into its slot,
         // whose boundary is set first (passes write interior points only;
@@ -55,14 +41,13 @@ int run_loop(int dtype, void* T, void* T2, const void* Ci, int nx, int ny, int n
         if (ckpt && k % C == 0 && k <= klast) {
             dst = static_cast<char*>(ckpt) + (size_t)(k / C - 1) * field_stride;
             rc = boundary_dispatch(dtype, dst, T, nx, ny, nz, st);
-            if (rc) return rc;
+            if (rc) return;
         }
-        rc = pass_dispatch(dtype, dst, cur, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, g_sr_step + (uint64_t)it, st);
-        if (rc) return rc;
+        rc = pass_dispatch(dtype, dst, cur, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, c.sr_step + (uint64_t)it, c,
+                           st);
         cur = dst;
-        it = k;
-    }
-    g_sr_step += (uint64_t)nt;
+    });
+    if (rc) return rc;
     if (want_result && cur != T) return copy_bytes(T, cur, fbytes, st);
     return DIFF3D_OK;
 }
@@ -137,49 +122,71 @@ int diff3d_copy(void* dst, const void* src, size_t bytes, void* stream)
     return copy_bytes(dst, src, bytes, as_stream(stream));
 }
 
-int diff3d_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
-                double rdy, double rdz, int dtype, void* stream)
+// Common checks of the forward entry points: dtype, pointers, grid, the
+// configuration, and T2 overlapping neither T nor Ci.
+static int check_step_args(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, int dtype,
+                           const diff3d_config& c)
 {
     if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
     if (!T2 || !T || !Ci || check_grid(nx, ny, nz)) return DIFF3D_EINVAL;
+    if (check_forward_config(c, dtype)) return DIFF3D_EINVAL;
     const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
     if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb)) return DIFF3D_EINVAL;
-    const int rc = step_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step, as_stream(stream));
-    g_sr_step += 1;
-    return rc;
+    return DIFF3D_OK;
+}
+
+int diff3d_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
+                double rdy, double rdz, int dtype, void* stream, const diff3d_config* cfg)
+{
+    const diff3d_config c = config_of(cfg);
+    const int rc = check_step_args(T2, T, Ci, nx, ny, nz, dtype, c);
+    if (rc) return rc;
+    return step_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, c.sr_step, c, as_stream(stream));
 }
 
 int diff3d_step2(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
-                 double rdy, double rdz, int dtype, void* stream)
+                 double rdy, double rdz, int dtype, void* stream, const diff3d_config* cfg)
 {
-    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
-    if (!T2 || !T || !Ci || check_grid(nx, ny, nz)) return DIFF3D_EINVAL;
-    const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
-    if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb)) return DIFF3D_EINVAL;
-    const int rc = pair_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, g_sr_step, as_stream(stream));
-    g_sr_step += 2;
-    return rc;
+    const diff3d_config c = config_of(cfg);
+    const int rc = check_step_args(T2, T, Ci, nx, ny, nz, dtype, c);
+    if (rc) return rc;
+    return pair_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, c.sr_step + 1, c, as_stream(stream));
 }
 
 int diff3d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
-                 double rdy, double rdz, int nsteps, int dtype, void* stream)
+                 double rdy, double rdz, int nsteps, int dtype, void* stream, const diff3d_config* cfg)
 {
-    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
-    if (!T2 || !T || !Ci || check_grid(nx, ny, nz)) return DIFF3D_EINVAL;
+    const diff3d_config c = config_of(cfg);
+    const int rc = check_step_args(T2, T, Ci, nx, ny, nz, dtype, c);
+    if (rc) return rc;
     if (nsteps < 1 || nsteps > DIFF3D_MAX_PASS_STEPS) return DIFF3D_EINVAL;
-    const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
-    if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb)) return DIFF3D_EINVAL;
-    const int rc =
-        pass_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, g_sr_step, as_stream(stream));
-    g_sr_step += (uint64_t)nsteps;
-    return rc;
+    return pass_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, c.sr_step, c,
+                         as_stream(stream));
+}
+
+int diff3d_pass_plan(int nx, int ny, int nz, int nt, int ckpt_every, int dtype, const diff3d_config* cfg,
+                     int* lengths, int max_lengths)
+{
+    const diff3d_config c = config_of(cfg);
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (check_grid(nx, ny, nz) || nt < 0 || ckpt_every < 0 || max_lengths < 0) return DIFF3D_EINVAL;
+    if (check_forward_config(c, dtype)) return DIFF3D_EINVAL;
+    int count = 0;
+    for_each_pass(dtype, nx, ny, nt, ckpt_every, nt - 1, c, [&](int, int n) {
+        if (lengths && count < max_lengths) lengths[count] = n;
+        ++count;
+    });
+    return count;
 }
 
 int diff3d_run(void* T, void* T2, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
-               double rdy, double rdz, int nt, int dtype, void* stream, void* ckpt, int ckpt_every)
+               double rdy, double rdz, int nt, int dtype, void* stream, void* ckpt, int ckpt_every,
+               const diff3d_config* cfg)
 {
+    const diff3d_config c = config_of(cfg);
     if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
     if (!T || !T2 || !Ci || check_grid(nx, ny, nz) || nt < 0) return DIFF3D_EINVAL;
+    if (check_forward_config(c, dtype)) return DIFF3D_EINVAL;
     if (ckpt && ckpt_every < 1) return DIFF3D_EINVAL;
     const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
     if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb) || overlap(T, fb, Ci, fb)) return DIFF3D_EINVAL;
@@ -192,27 +199,34 @@ int diff3d_run(void* T, void* T2, const void* Ci, int nx, int ny, int nz, double
     }
     if (nt == 0) return DIFF3D_OK;
     return run_loop(dtype, T, T2, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nt, as_stream(stream), ckpt, ckpt_every,
-                    stride, nt - 1, true);
+                    stride, nt - 1, true, c);
 }
 
-size_t diff3d_adjoint_workspace_bytes(int nx, int ny, int nz, int nt, int ckpt_every, int dtype)
+size_t diff3d_adjoint_workspace_bytes(int nx, int ny, int nz, int nt, int ckpt_every, int dtype,
+                                      const diff3d_config* cfg)
 {
+    const diff3d_config c = config_of(cfg);
     if (!known_dtype(dtype) || check_grid(nx, ny, nz) || nt < 0 || ckpt_every < 1) return 0;
+    if (check_forward_config(c, dtype) || check_adjoint_config(c, dtype)) return 0;
     const size_t stride = align256(npoints(nx, ny, nz) * elem_size(dtype));
     const int nck = nck_of(nt, ckpt_every);
-    const size_t fields = (size_t)(nck > 1 ? nck - 1 : 0) + (size_t)(ckpt_every - 1) + 1;
+    const size_t fields =
+        (size_t)(nck > 1 ? nck - 1 : 0) + (size_t)recompute_fields(dtype, nt, ckpt_every, c) + 1;
     return fields * stride;
 }
 
 int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* gT0, void* gCi, void* workspace,
                        size_t ws_bytes, int ckpt_ready, int nx, int ny, int nz, double lam, double dt, double rdx,
-                       double rdy, double rdz, int nt, int ckpt_every, int dtype, void* stream)
+                       double rdy, double rdz, int nt, int ckpt_every, int dtype, void* stream,
+                       const diff3d_config* cfg)
 {
+    const diff3d_config c = config_of(cfg);
     if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
     if (dtype != DIFF3D_F64 && dtype != DIFF3D_F32) return DIFF3D_EDTYPE;
     if (!T0 || !Ci || !gTnt || !gT0 || !gCi || check_grid(nx, ny, nz) || nt < 0 || ckpt_every < 1)
         return DIFF3D_EINVAL;
-    const size_t need = diff3d_adjoint_workspace_bytes(nx, ny, nz, nt, ckpt_every, dtype);
+    if (check_forward_config(c, dtype) || check_adjoint_config(c, dtype)) return DIFF3D_EINVAL;
+    const size_t need = diff3d_adjoint_workspace_bytes(nx, ny, nz, nt, ckpt_every, dtype, cfg);
     if (!workspace || ws_bytes < need) return DIFF3D_EWORKSPACE;
     const size_t fb = npoints(nx, ny, nz) * elem_size(dtype);
     const void* ins[3] = {T0, Ci, gTnt};
@@ -232,9 +246,10 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
     char* ws = static_cast<char*>(workspace);
     const int nck = nck_of(nt, C);
     auto slot = [&](int j) -> void* { return ws + (size_t)(j - 1) * stride; };   // T_{jC}, j >= 1
-    char* seg0 = ws + (size_t)(nck > 1 ? nck - 1 : 0) * stride;                  // C-1 recompute fields
+    const int nseg = recompute_fields(dtype, nt, C, c);
+    char* seg0 = ws + (size_t)(nck > 1 ? nck - 1 : 0) * stride;                  // recompute fields
     auto seg = [&](int i) -> void* { return seg0 + (size_t)i * stride; };
-    void* W = seg0 + (size_t)(C - 1) * stride;                                   // adjoint ping-pong
+    void* W = seg0 + (size_t)nseg * stride;                                      // adjoint ping-pong
 
     int rc = zero_bytes(gCi, fb, st);
     if (rc) return rc;
@@ -245,23 +260,22 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
         rc = copy_bytes(W, T0, fb, st);
         const int last = (nck - 1) * C;
         if (!rc) rc = run_loop(dtype, W, gT0, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, last, st, ws, C, stride, last,
-                               false);
+                               false, c);
         if (rc) return rc;
     }
     // recompute fields need T0's boundary (steps write interior points only)
-    const int segn = (C - 1 < nt - 1 ? C - 1 : nt - 1);
-    for (int i = 0; i < segn; ++i) {
+    for (int i = 0; i < nseg; ++i) {
         rc = boundary_dispatch(dtype, seg(i), T0, nx, ny, nz, st);
         if (rc) return rc;
     }
 
-    if (g_kernel == DIFF3D_KERNEL_TBS || g_kernel == DIFF3D_KERNEL_AUTO) {
+    if (rev_fused(c)) {
         // Fused reverse passes of P steps (the first pass of a segment takes
         // the remainder): only the states at pass starts are recomputed (by
         // forward passes of the same lengths), the pass recomputes the rest
         // on chip.  lambda alternates between gT0 and W so that the last
         // launch writes gT0.
-        const int P = rev_pass_steps(dtype);
+        const int P = rev_pass_steps(dtype, c);
         auto npass = [&](int len) { return (len + P - 1) / P; };
         long nlaunch = 0;
         for (int j = nck - 1; j >= 0; --j) nlaunch += npass(((j * C + C < nt) ? j * C + C : nt) - j * C);
@@ -277,7 +291,7 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
             const void* src = base;
             for (int i = 1; i < m; ++i) {
                 rc = pass_dispatch(dtype, seg(i - 1), src, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, i == 1 ? r : P, 0,
-                                   st);
+                                   c, st);
                 if (rc) return rc;
                 src = seg(i - 1);
             }
@@ -285,8 +299,8 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
                 const int n = i == 0 ? r : P;
                 const void* Tk = i == 0 ? base : seg(i - 1);
                 void* out = ((nlaunch - 1 - launch) % 2 == 0) ? gT0 : W;
-                rc = n >= 2 ? rev_dispatch(dtype, n, out, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st)
-                            : adj_dispatch(dtype, out, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+                rc = n >= 2 ? rev_dispatch(dtype, n, out, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st)
+                            : adj_dispatch(dtype, out, lin, Ci, Tk, gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
                 if (rc) return rc;
                 lin = out;
                 ++launch;
@@ -297,7 +311,7 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
 
     // adjoint launches (two steps per launch inside a segment where enabled);
     // lambda alternates between gT0 and W so that the last launch writes gT0
-    const bool apairs = g_kernel == DIFF3D_KERNEL_AUTO || g_kernel == DIFF3D_KERNEL_TB2;
+    const bool apairs = c.kernel == DIFF3D_KERNEL_TB2;
     long nlaunch = 0;
     for (int j = nck - 1; j >= 0; --j) {
         const int len = ((j * C + C < nt) ? j * C + C : nt) - j * C;
@@ -313,15 +327,15 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
         // where possible (one pass writing both the intermediate and the
         // second state), the two-step kernel unless single steps are selected
         const void* src = base;
-        const bool pairs = g_kernel == DIFF3D_KERNEL_AUTO || g_kernel == DIFF3D_KERNEL_TB2;
+        const bool pairs = c.kernel == DIFF3D_KERNEL_TB2;
         for (int k = s; k < e - 1;) {
             if (pairs && k + 2 <= e - 1) {
                 rc = pair_mid_dispatch(dtype, seg(k - s + 1), seg(k - s), src, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz,
-                                       st);
+                                       c, st);
                 src = seg(k - s + 1);
                 k += 2;
             } else {
-                rc = step_dispatch(dtype, seg(k - s), src, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, 0, st);
+                rc = step_dispatch(dtype, seg(k - s), src, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, 0, c, st);
                 src = seg(k - s);
                 k += 1;
             }
@@ -332,10 +346,10 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
             void* out = ((nlaunch - 1 - launch) % 2 == 0) ? gT0 : W;
             if (apairs && k - 1 >= s) {
                 rc = adj2_dispatch(dtype, out, lin, Ci, state(k), state(k - 1), gCi, nx, ny, nz, lam, dt, rdx, rdy,
-                                   rdz, st);
+                                   rdz, c, st);
                 k -= 2;
             } else {
-                rc = adj_dispatch(dtype, out, lin, Ci, state(k), gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+                rc = adj_dispatch(dtype, out, lin, Ci, state(k), gCi, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
                 k -= 1;
             }
             if (rc) return rc;
@@ -344,28 +358,6 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
         }
     }
     return DIFF3D_OK;
-}
-
-int diff3d_set_kernel(int kernel)
-{
-    if (kernel < DIFF3D_KERNEL_AUTO || kernel > DIFF3D_KERNEL_TBS) return DIFF3D_EINVAL;
-    g_kernel = kernel;
-    return DIFF3D_OK;
-}
-
-int diff3d_get_kernel(void) { return g_kernel; }
-
-int diff3d_set_pass_steps(int nsteps)
-{
-    if (nsteps < 0 || nsteps == 1 || nsteps > DIFF3D_MAX_PASS_STEPS) return DIFF3D_EINVAL;
-    g_pass_steps = nsteps;
-    return DIFF3D_OK;
-}
-
-void diff3d_set_sr_seed(uint64_t seed, uint64_t step0)
-{
-    g_sr_seed = seed;
-    g_sr_step = step0;
 }
 
 // ------------------------------------------------------------- 2-D form

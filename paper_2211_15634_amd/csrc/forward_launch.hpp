@@ -1,5 +1,6 @@
 // Forward step launches: tile configuration tables and defaults per dtype,
-// the single-step, two-step and S-step launchers and their dispatch.
+// the single-step, two-step and S-step launchers, their dispatch, the pass
+// plan of the time loop and the validation of the caller's overrides.
 #pragma once
 
 #include "launch_plan.hpp"
@@ -11,9 +12,12 @@ namespace diff3d {
 namespace {
 
 // ------------------------------------------------------------------ forward
+// Arguments of a forward launch.  `draw_step` is the step index of the
+// stochastic rounding of the state the launch stores (the index of the last
+// step it takes).
 template <int DT>
 StepArgs<DT> make_step_args(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
-                            double rdx, double rdy, double rdz, uint64_t step_index)
+                            double rdx, double rdy, double rdz, uint64_t sr_seed, uint64_t draw_step)
 {
     using S = typename Traits<DT>::S;
     using C = typename Traits<DT>::C;
@@ -30,10 +34,10 @@ StepArgs<DT> make_step_args(void* T2, const void* T, const void* Ci, int nx, int
     a.cx = (C)(rdx * rdx);
     a.cy = (C)(rdy * rdy);
     a.cz = (C)(rdz * rdz);
-    a.sr.k0 = (uint32_t)g_sr_seed;
-    a.sr.k1 = (uint32_t)(g_sr_seed >> 32);
-    a.sr.s0 = (uint32_t)step_index;
-    a.sr.s1 = (uint32_t)(step_index >> 32);
+    a.sr.k0 = (uint32_t)sr_seed;
+    a.sr.k1 = (uint32_t)(sr_seed >> 32);
+    a.sr.s0 = (uint32_t)draw_step;
+    a.sr.s1 = (uint32_t)(draw_step >> 32);
     return a;
 }
 
@@ -64,6 +68,19 @@ template <> struct FwdDefaults<DIFF3D_BF16_RNE> {
 };
 constexpr ZKey kNarrow{1, 4, 4, 0};
 
+// Is a (V, R, NW, NT) key instantiated for storage of `size` bytes?
+inline bool fwd_has(int size, const ZKey& k)
+{
+#define DIFF3D_HAS(v, r, nw, nt) || key_eq(k, v, r, nw, nt)
+    switch (size) {
+    case 8: return false DIFF3D_FWD_CFGS_8(DIFF3D_HAS);
+    case 4: return false DIFF3D_FWD_CFGS_4(DIFF3D_HAS);
+    case 2: return false DIFF3D_FWD_CFGS_2(DIFF3D_HAS);
+    default: return false;
+    }
+#undef DIFF3D_HAS
+}
+
 template <int DT, int V, int R, int NW, int NT>
 int launch_zmarch_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req, int zdef)
 {
@@ -73,16 +90,14 @@ int launch_zmarch_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req, int z
 }
 
 template <int DT>
-int launch_zmarch(const StepArgs<DT>& a, hipStream_t st)
+int launch_zmarch(const StepArgs<DT>& a, const diff3d_config& c, hipStream_t st)
 {
     using S = typename Traits<DT>::S;
-    ZKey k = FwdDefaults<DT>::wide;
-    env_key("DIFF3D_ZCFG", k);
-    if (env_int("DIFF3D_NARROW", 0) || !vec_ok<S>(a.nx, k.V, a.T, a.T2, a.Ci)) k = kNarrow;
-    const int zlen = env_int("DIFF3D_ZLEN", 0);
+    ZKey k = zkey_of(c.zmarch, FwdDefaults<DT>::wide);
+    if (c.narrow || !vec_ok<S>(a.nx, k.V, a.T, a.T2, a.Ci)) k = kNarrow;
     const int zdef = FwdDefaults<DT>::zdef;
 #define DIFF3D_TRY(v, r, nw, nt) \
-    if (key_eq(k, v, r, nw, nt)) return launch_zmarch_cfg<DT, v, r, nw, nt>(a, st, zlen, zdef);
+    if (key_eq(k, v, r, nw, nt)) return launch_zmarch_cfg<DT, v, r, nw, nt>(a, st, c.zmarch.zlen, zdef);
     if constexpr (sizeof(S) == 8) {
         DIFF3D_FWD_CFGS_8(DIFF3D_TRY)
     } else if constexpr (sizeof(S) == 4) {
@@ -91,7 +106,7 @@ int launch_zmarch(const StepArgs<DT>& a, hipStream_t st)
         DIFF3D_FWD_CFGS_2(DIFF3D_TRY)
     }
 #undef DIFF3D_TRY
-    return DIFF3D_EINVAL;   // configuration not instantiated (tuning override only)
+    return DIFF3D_EINVAL;   // not reached: overrides are validated before any launch
 }
 
 // Two-step (temporal-blocked) configurations.
@@ -113,6 +128,18 @@ template <> struct Tb2Defaults<DIFF3D_BF16_RNE> {
 };
 constexpr ZKey kNarrowTb2{1, 4, 4, 1};
 
+inline bool tb2_has(int size, const ZKey& k)
+{
+#define DIFF3D_HAS(v, r, nw, nt) || key_eq(k, v, r, nw, nt)
+    switch (size) {
+    case 8: return false DIFF3D_TB2_CFGS_8(DIFF3D_HAS);
+    case 4: return false DIFF3D_TB2_CFGS_4(DIFF3D_HAS);
+    case 2: return false DIFF3D_TB2_CFGS_2(DIFF3D_HAS);
+    default: return false;
+    }
+#undef DIFF3D_HAS
+}
+
 template <int DT, int V, int R, int NW, int NT, bool MID>
 int launch_tb2_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req, int zdef)
 {
@@ -122,16 +149,14 @@ int launch_tb2_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req, int zdef
 }
 
 template <int DT, bool MID>
-int launch_tb2(const StepArgs<DT>& a, hipStream_t st)
+int launch_tb2(const StepArgs<DT>& a, const diff3d_config& c, hipStream_t st)
 {
     using S = typename Traits<DT>::S;
-    ZKey k = Tb2Defaults<DT>::wide;
-    env_key("DIFF3D_TCFG", k);
-    if (env_int("DIFF3D_NARROW", 0) || !vec_ok<S>(a.nx, k.V, a.T, a.T2, a.Ci)) k = kNarrowTb2;
-    const int zlen = env_int("DIFF3D_TZLEN", 0);
+    ZKey k = zkey_of(c.tb2, Tb2Defaults<DT>::wide);
+    if (c.narrow || !vec_ok<S>(a.nx, k.V, a.T, a.T2, a.Ci)) k = kNarrowTb2;
     const int zdef = Tb2Defaults<DT>::zdef;
 #define DIFF3D_TRY(v, r, nw, nt) \
-    if (key_eq(k, v, r, nw, nt)) return launch_tb2_cfg<DT, v, r, nw, nt, MID>(a, st, zlen, zdef);
+    if (key_eq(k, v, r, nw, nt)) return launch_tb2_cfg<DT, v, r, nw, nt, MID>(a, st, c.tb2.zlen, zdef);
     if constexpr (sizeof(S) == 8) {
         DIFF3D_TB2_CFGS_8(DIFF3D_TRY)
     } else if constexpr (sizeof(S) == 4) {
@@ -143,44 +168,50 @@ int launch_tb2(const StepArgs<DT>& a, hipStream_t st)
     return DIFF3D_EINVAL;
 }
 
-// Two steps T -> T2 (T^{k+2}); SR step indices step_index and step_index+1.
+// Two steps T -> T2 (T^{k+2}); the stored state draws with `draw_step`.
 template <int DT>
 int launch_pair(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
-                double rdy, double rdz, uint64_t step_index, hipStream_t st)
+                double rdy, double rdz, uint64_t draw_step, const diff3d_config& c, hipStream_t st)
 {
-    const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index);
-    return launch_tb2<DT, false>(a, st);
+    const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, c.sr_seed, draw_step);
+    return launch_tb2<DT, false>(a, c, st);
 }
 
 // Two steps T -> Tmid (T^{k+1}) and T2 (T^{k+2}), interior points of both.
 template <int DT>
 int launch_pair_mid(void* T2, void* Tmid, const void* T, const void* Ci, int nx, int ny, int nz, double lam,
-                    double dt, double rdx, double rdy, double rdz, hipStream_t st)
+                    double dt, double rdx, double rdy, double rdz, const diff3d_config& c, hipStream_t st)
 {
-    StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, 0);
+    StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, 0, 0);
     a.Tmid = static_cast<typename Traits<DT>::S*>(Tmid);
-    return launch_tb2<DT, true>(a, st);
+    return launch_tb2<DT, true>(a, c, st);
 }
 
 int pair_mid_dispatch(int dtype, void* T2, void* Tmid, const void* T, const void* Ci, int nx, int ny, int nz,
-                      double lam, double dt, double rdx, double rdy, double rdz, hipStream_t st)
+                      double lam, double dt, double rdx, double rdy, double rdz, const diff3d_config& c,
+                      hipStream_t st)
 {
     switch (dtype) {
-    case DIFF3D_F64: return launch_pair_mid<DIFF3D_F64>(T2, Tmid, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
-    case DIFF3D_F32: return launch_pair_mid<DIFF3D_F32>(T2, Tmid, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, st);
+    case DIFF3D_F64:
+        return launch_pair_mid<DIFF3D_F64>(T2, Tmid, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
+    case DIFF3D_F32:
+        return launch_pair_mid<DIFF3D_F32>(T2, Tmid, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, c, st);
     default: return DIFF3D_EDTYPE;
     }
 }
 
 int pair_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
-                  double rdx, double rdy, double rdz, uint64_t step_index, hipStream_t st)
+                  double rdx, double rdy, double rdz, uint64_t draw_step, const diff3d_config& c, hipStream_t st)
 {
     switch (dtype) {
-    case DIFF3D_F64: return launch_pair<DIFF3D_F64>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
-    case DIFF3D_F32: return launch_pair<DIFF3D_F32>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
-    case DIFF3D_BF16: return launch_pair<DIFF3D_BF16>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    case DIFF3D_F64:
+        return launch_pair<DIFF3D_F64>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw_step, c, st);
+    case DIFF3D_F32:
+        return launch_pair<DIFF3D_F32>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw_step, c, st);
+    case DIFF3D_BF16:
+        return launch_pair<DIFF3D_BF16>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw_step, c, st);
     case DIFF3D_BF16_RNE:
-        return launch_pair<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+        return launch_pair<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw_step, c, st);
     default: return DIFF3D_EDTYPE;
     }
 }
@@ -210,6 +241,18 @@ template <> struct TbsDefaults<DIFF3D_BF16_RNE> {
     static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 1024, 0}, {3, 64, 32, 1024, 0}, {4, 64, 32, 1024, 0}};
 };
 
+inline bool tbs_has(int size, const SKey& k)
+{
+#define DIFF3D_HAS(s, w0, h0, nth, nt) || skey_eq(k, s, w0, h0, nth, nt)
+    switch (size) {
+    case 8: return false DIFF3D_TBS_CFGS_8(DIFF3D_HAS);
+    case 4: return false DIFF3D_TBS_CFGS_4(DIFF3D_HAS);
+    case 2: return false DIFF3D_TBS_CFGS_2(DIFF3D_HAS);
+    default: return false;
+    }
+#undef DIFF3D_HAS
+}
+
 template <int DT, int S, int W0, int H0, int NTH, int NT>
 int launch_tbs_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req)
 {
@@ -224,13 +267,12 @@ int launch_tbs_cfg(const StepArgs<DT>& a, hipStream_t st, int zlen_req)
 
 // S steps T -> T2 in one pass (2 <= S <= DIFF3D_MAX_PASS_STEPS).
 template <int DT>
-int launch_tbs(const StepArgs<DT>& a, int nsteps, hipStream_t st)
+int launch_tbs(const StepArgs<DT>& a, int nsteps, const diff3d_config& c, hipStream_t st)
 {
     using Sz = typename Traits<DT>::S;
     if (nsteps < 2 || nsteps > DIFF3D_MAX_PASS_STEPS) return DIFF3D_EINVAL;
-    SKey k = TbsDefaults<DT>::key[nsteps];
-    env_skey("DIFF3D_SCFG", k);
-    const int zlen = env_int("DIFF3D_SZLEN", 0);
+    const SKey k = skey_of(c.tbs, nsteps, TbsDefaults<DT>::key[nsteps]);
+    const int zlen = szlen_of(c.tbs, nsteps);
 #define DIFF3D_TRY(s, w0, h0, nth, nt) \
     if (skey_eq(k, s, w0, h0, nth, nt)) return launch_tbs_cfg<DT, s, w0, h0, nth, nt>(a, st, zlen);
     if constexpr (sizeof(Sz) == 8) {
@@ -246,46 +288,51 @@ int launch_tbs(const StepArgs<DT>& a, int nsteps, hipStream_t st)
 
 template <int DT>
 int launch_multi(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
-                 double rdy, double rdz, int nsteps, uint64_t step_index, hipStream_t st)
+                 double rdy, double rdz, int nsteps, uint64_t draw_step, const diff3d_config& c, hipStream_t st)
 {
-    const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index);
-    return launch_tbs<DT>(a, nsteps, st);
+    const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, c.sr_seed, draw_step);
+    return launch_tbs<DT>(a, nsteps, c, st);
 }
 
 int multi_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
-                   double rdx, double rdy, double rdz, int nsteps, uint64_t step_index, hipStream_t st)
+                   double rdx, double rdy, double rdz, int nsteps, uint64_t draw_step, const diff3d_config& c,
+                   hipStream_t st)
 {
     switch (dtype) {
     case DIFF3D_F64:
-        return launch_multi<DIFF3D_F64>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, step_index, st);
+        return launch_multi<DIFF3D_F64>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, draw_step, c, st);
     case DIFF3D_F32:
-        return launch_multi<DIFF3D_F32>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, step_index, st);
+        return launch_multi<DIFF3D_F32>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, draw_step, c, st);
     case DIFF3D_BF16:
-        return launch_multi<DIFF3D_BF16>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, step_index, st);
+        return launch_multi<DIFF3D_BF16>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, draw_step, c, st);
     case DIFF3D_BF16_RNE:
-        return launch_multi<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, step_index, st);
+        return launch_multi<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, nsteps, draw_step, c,
+                                             st);
     default: return DIFF3D_EDTYPE;
     }
 }
 
 template <int DT>
 int launch_step(void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
-                double rdy, double rdz, uint64_t step_index, hipStream_t st)
+                double rdy, double rdz, uint64_t draw_step, const diff3d_config& c, hipStream_t st)
 {
-    const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index);
-    if (g_kernel == DIFF3D_KERNEL_NAIVE) return launch_naive<DT>(a, st);
-    return launch_zmarch<DT>(a, st);
+    const StepArgs<DT> a = make_step_args<DT>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, c.sr_seed, draw_step);
+    if (c.kernel == DIFF3D_KERNEL_NAIVE) return launch_naive<DT>(a, st);
+    return launch_zmarch<DT>(a, c, st);
 }
 
 int step_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
-                  double rdx, double rdy, double rdz, uint64_t step_index, hipStream_t st)
+                  double rdx, double rdy, double rdz, uint64_t draw_step, const diff3d_config& c, hipStream_t st)
 {
     switch (dtype) {
-    case DIFF3D_F64: return launch_step<DIFF3D_F64>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
-    case DIFF3D_F32: return launch_step<DIFF3D_F32>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
-    case DIFF3D_BF16: return launch_step<DIFF3D_BF16>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+    case DIFF3D_F64:
+        return launch_step<DIFF3D_F64>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw_step, c, st);
+    case DIFF3D_F32:
+        return launch_step<DIFF3D_F32>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw_step, c, st);
+    case DIFF3D_BF16:
+        return launch_step<DIFF3D_BF16>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw_step, c, st);
     case DIFF3D_BF16_RNE:
-        return launch_step<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
+        return launch_step<DIFF3D_BF16_RNE>(T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw_step, c, st);
     default: return DIFF3D_EDTYPE;
     }
 }
@@ -293,16 +340,19 @@ int step_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, in
 // n steps in one pass: a single step, the two-step kernel, or the S-step
 // kernel (always for n >= 3; for n = 2 when it is selected, and under AUTO
 // for the BF16 forms, where it is about twice as fast per step at 512^3;
-// for FP64 and FP32 the two-step kernel is faster).
+// for FP64 and FP32 the two-step kernel is faster).  `first_step` is the
+// index of the pass's first step; the stored state draws with the index of
+// its last.
 int pass_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, int nz, double lam, double dt,
-                  double rdx, double rdy, double rdz, int n, uint64_t step_index, hipStream_t st)
+                  double rdx, double rdy, double rdz, int n, uint64_t first_step, const diff3d_config& c,
+                  hipStream_t st)
 {
-    if (n == 1) return step_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
-    const bool tbs2 = g_kernel == DIFF3D_KERNEL_TBS ||
-                      (g_kernel == DIFF3D_KERNEL_AUTO && (dtype == DIFF3D_BF16 || dtype == DIFF3D_BF16_RNE));
-    if (n == 2 && !tbs2)
-        return pair_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, step_index, st);
-    return multi_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, step_index, st);
+    const uint64_t draw = first_step + (uint64_t)(n - 1);
+    if (n == 1) return step_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw, c, st);
+    const bool tbs2 = c.kernel == DIFF3D_KERNEL_TBS ||
+                      (c.kernel == DIFF3D_KERNEL_AUTO && (dtype == DIFF3D_BF16 || dtype == DIFF3D_BF16_RNE));
+    if (n == 2 && !tbs2) return pair_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, draw, c, st);
+    return multi_dispatch(dtype, T2, T, Ci, nx, ny, nz, lam, dt, rdx, rdy, rdz, n, draw, c, st);
 }
 
 // FP32 four-step passes lose to three-step ones on large x-y planes
@@ -322,20 +372,67 @@ int tbs_default_steps(int dtype, int nx, int ny)
 }
 
 // Steps per pass of diff3d_run for the selected kernel.  AUTO uses the
-// S-step kernel's measured best pass length: 4 for FP64 and FP32 (3 for
-// FP32 on planes above 768^2 points), 4 for
-// BF16 with round-to-nearest (two workgroups per CU: 103 us per step against
-// 207 for single steps at 512^3), 3 for BF16 with stochastic rounding (bound
-// by the Philox draws: 253 against 300 us).
-int run_pass_steps(int dtype, int nx, int ny)
+// S-step kernel's measured best pass length for the dtype (and, for FP32,
+// the plane size).
+int run_pass_steps(int dtype, int nx, int ny, const diff3d_config& c)
 {
-    switch (g_kernel) {
+    switch (c.kernel) {
     case DIFF3D_KERNEL_NAIVE:
     case DIFF3D_KERNEL_ZMARCH: return 1;
     case DIFF3D_KERNEL_TB2: return 2;
-    case DIFF3D_KERNEL_TBS: return g_pass_steps ? g_pass_steps : tbs_default_steps(dtype, nx, ny);
+    case DIFF3D_KERNEL_TBS: return c.pass_steps ? c.pass_steps : tbs_default_steps(dtype, nx, ny);
     default: return tbs_default_steps(dtype, nx, ny);
     }
+}
+
+// The pass lengths of the time loop (diff3d_pass_plan): passes of at most P
+// steps that never cross a checkpointed state (multiples of C at or below
+// klast; C = 0: none); with the default pass length each stretch between
+// checkpoints is split into passes of near-equal length (14 steps with
+// P = 4 as 4, 4, 3, 3 rather than 4, 4, 4, 2: short passes cost more per
+// step), with a set length into passes of exactly that length.  Calls
+// f(first_step, length) for each pass in order.
+template <class F>
+void for_each_pass(int dtype, int nx, int ny, int nt, int C, int klast, const diff3d_config& c, F&& f)
+{
+    const int P = run_pass_steps(dtype, nx, ny, c);
+    const bool even = !(c.kernel == DIFF3D_KERNEL_TBS && c.pass_steps);
+    for (int it = 0; it < nt;) {
+        int end = nt;
+        if (C > 0) {
+            const int next = (it / C + 1) * C;   // next checkpointed step
+            if (next <= klast && next < end) end = next;
+        }
+        const int rem = end - it;
+        const int m = (rem + P - 1) / P;
+        const int n = even ? (rem + m - 1) / m : min(P, rem);
+        f(it, n);
+        it += n;
+    }
+}
+
+// ------------------------------------------------------------------ validation
+// The caller's configuration must name a known kernel, a pass length the
+// S-step kernel has and only instantiated tile overrides for this storage
+// size; nothing is launched otherwise.
+int check_forward_config(const diff3d_config& c, int dtype)
+{
+    if (c.kernel < DIFF3D_KERNEL_AUTO || c.kernel > DIFF3D_KERNEL_TBS) return DIFF3D_EINVAL;
+    if (c.pass_steps != 0 && (c.pass_steps < 2 || c.pass_steps > DIFF3D_MAX_PASS_STEPS)) return DIFF3D_EINVAL;
+    if (c.narrow != 0 && c.narrow != 1) return DIFF3D_EINVAL;
+    if (c.reserved != 0) return DIFF3D_EINVAL;
+    const int size = (int)elem_size(dtype);
+    const diff3d_tile* zt[2] = {&c.zmarch, &c.tb2};
+    for (int i = 0; i < 2; ++i) {
+        if (zt[i]->steps != 0 || zt[i]->zlen < 0) return DIFF3D_EINVAL;
+    }
+    if (tile_set(c.zmarch) && !fwd_has(size, zkey_of(c.zmarch, kNarrow))) return DIFF3D_EINVAL;
+    if (tile_set(c.tb2) && !tb2_has(size, zkey_of(c.tb2, kNarrowTb2))) return DIFF3D_EINVAL;
+    if (c.tbs.zlen < 0) return DIFF3D_EINVAL;
+    if (c.tbs.steps != 0 && (c.tbs.steps < 2 || c.tbs.steps > DIFF3D_MAX_PASS_STEPS)) return DIFF3D_EINVAL;
+    if (tile_set(c.tbs) && (c.tbs.steps == 0 || !tbs_has(size, skey_of(c.tbs, c.tbs.steps, SKey{0, 0, 0, 0, 0}))))
+        return DIFF3D_EINVAL;
+    return DIFF3D_OK;
 }
 
 }  // namespace

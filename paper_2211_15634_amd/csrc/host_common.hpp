@@ -1,21 +1,18 @@
-// Host side of the library: process-wide settings and argument helpers.
-// Everything here is internal to the library (one translation unit).
+// Host side of the library: argument helpers and the per-call configuration.
+// Everything here is internal to the library (one translation unit); the
+// library keeps no state between calls.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include "diff3d.h"
 
 namespace diff3d {
 namespace {
-
-int g_kernel = DIFF3D_KERNEL_AUTO;
-int g_pass_steps = 0;   // steps per pass of the S-step kernel in diff3d_run (0 = dtype default)
-uint64_t g_sr_seed = 0x5EEDu;
-uint64_t g_sr_step = 0;
 
 constexpr size_t kMaxPoints = (size_t)1 << 40;
 
@@ -56,11 +53,18 @@ inline bool overlap(const void* a, size_t na, const void* b, size_t nb)
     return pa < pb + nb && pb < pa + na;
 }
 
-int env_int(const char* name, int dflt)
+// The caller's configuration, or the defaults (a zero-filled struct).
+inline diff3d_config config_of(const diff3d_config* cfg)
 {
-    const char* s = getenv(name);
-    if (!s || !*s) return dflt;
-    return atoi(s);
+    diff3d_config c;
+    memset(&c, 0, sizeof c);
+    if (cfg) c = *cfg;
+    return c;
+}
+
+inline bool tile_set(const diff3d_tile& t)
+{
+    return t.p[0] || t.p[1] || t.p[2] || t.p[3];
 }
 
 }  // namespace

@@ -1,8 +1,7 @@
 // Launch planning shared by the kernels: tiles over x-y, z-chunks, rounds
-// of resident workgroups, tile configuration keys and their overrides.
+// of resident workgroups, tile configuration keys and the caller's
+// overrides of them.
 #pragma once
-
-#include <stdio.h>
 
 #include <atomic>
 
@@ -54,17 +53,10 @@ inline bool key_eq(const ZKey& a, int V, int R, int NW, int NT)
     return a.V == V && a.R == R && a.NW == NW && a.NT == NT;
 }
 
-// Configuration override "V,R,NW[,NT]" from the environment (tuning only).
-inline bool env_key(const char* name, ZKey& k)
+// The override of a tile (V, R, NW, NT) family, or the default.
+inline ZKey zkey_of(const diff3d_tile& t, const ZKey& dflt)
 {
-    const char* s = getenv(name);
-    if (!s || !*s) return false;
-    ZKey r{0, 0, 0, 0};
-    const int got = sscanf(s, "%d,%d,%d,%d", &r.V, &r.R, &r.NW, &r.NT);
-    if (got < 3) return false;
-    if (got == 3) r.NT = 0;
-    k = r;
-    return true;
+    return tile_set(t) ? ZKey{t.p[0], t.p[1], t.p[2], t.p[3]} : dflt;
 }
 
 // Vector width V is usable when rows start on V-element boundaries and all
@@ -86,17 +78,18 @@ inline bool skey_eq(const SKey& a, int S, int W0, int H0, int NTH, int NT)
     return a.S == S && a.W0 == W0 && a.H0 == H0 && a.NTH == NTH && a.NT == NT;
 }
 
-// Override "W0,H0,NTH[,NT]" for the S-step kernel from the environment
-// (tuning only; S is the pass length).
-inline bool env_skey(const char* name, SKey& k)
+// The override of the S-step or fused reverse kernel for passes of S
+// steps (a set override names the pass length it applies to), or the
+// default; and the z-chunk length for such passes.
+inline SKey skey_of(const diff3d_tile& t, int S, const SKey& dflt)
 {
-    const char* s = getenv(name);
-    if (!s || !*s) return false;
-    SKey r{k.S, 0, 0, 0, 1};
-    const int got = sscanf(s, "%d,%d,%d,%d", &r.W0, &r.H0, &r.NTH, &r.NT);
-    if (got < 3) return false;
-    k = r;
-    return true;
+    if (tile_set(t) && t.steps == S) return SKey{S, t.p[0], t.p[1], t.p[2], t.p[3]};
+    return dflt;
+}
+
+inline int szlen_of(const diff3d_tile& t, int S)
+{
+    return (t.steps == 0 || t.steps == S) ? t.zlen : 0;
 }
 
 // Workgroups of `kernel` (nth threads) resident at once on the current

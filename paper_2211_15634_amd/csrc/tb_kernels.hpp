@@ -1,9 +1,9 @@
 // Two time steps per pass over HBM (temporal blocking) for the explicit 3-D
 // heat-diffusion step.  T^{k+2} is computed from T^k with the same
-// operations, in the same order, as two single steps: the intermediate
-// T^{k+1} is rounded exactly as storing it would round it (stochastic
-// rounding draws the same Philox bits for the same point and step), so the
-// result is bit-identical to two launches of the single-step kernel.
+// operations, in the same order, as two single steps; the intermediate
+// T^{k+1} stays in the compute type on chip, so FP64 and FP32 results are
+// bit-identical to two launches of the single-step kernel and BF16 rounds
+// once per pass (the stored state draws with the step index in a.sr).
 #pragma once
 
 #include <type_traits>
@@ -37,6 +37,7 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
     constexpr int WYL = 0, WYH = NW - 1, WXL = 1, WXR = 2;
     static_assert(NW >= 4, "the four ring roles need four distinct waves");
     static_assert(TY + 2 <= 64, "ring columns are held one point per lane");
+    static_assert(!MID || DT == DIFF3D_F64 || DT == DIFF3D_F32, "the intermediate is stored exactly only for FP64/FP32");
     __shared__ C lA[2][TY + 4][TX + 4];   // T^k plane, origin (y0 - 2, x0 - 2)
     __shared__ C lB[2][TY + 2][TX + 2];   // T^{k+1} plane, origin (y0 - 1, x0 - 1)
 
@@ -75,20 +76,10 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
     const bool xload1 = xrole && xc1 >= 0 && xc1 < nx && yx >= 0 && yx < ny;
     const bool xload2 = xrole && xmid && xc2 >= 0 && xc2 < nx && yx >= 0 && yx < ny;
 
-    SrState sr1 = a.sr, sr2 = a.sr;
-    sr2.s0 = a.sr.s0 + 1u;
-    sr2.s1 = a.sr.s1 + (sr2.s0 == 0u ? 1u : 0u);
-
     using Rows = C[R][V];
     using Vec = C[V];
     auto interior = [&](int x, int y, int z) __attribute__((always_inline)) {
         return x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2 && z >= 1 && z <= nz - 2;
-    };
-    // the value a single step would have stored and the next step loaded
-    auto as_stored = [&](C v, size_t idx, const SrState& sr) __attribute__((always_inline)) -> C {
-        uint32_t rnd = 0;
-        if constexpr (Tr::sr) rnd = sr_word(sr_block(sr, idx >> 3), (unsigned)(idx & 7));
-        return Tr::load(Tr::store(v, rnd));
     };
     auto vld = [&](const S* base, int x, int y, int z, Vec& dst, bool ok, auto nt) __attribute__((always_inline)) {
         if (ok && z >= 0 && z < nz) {
@@ -205,8 +196,7 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
                     const C xp = v < V - 1 ? t1[r][v + 1] : lA[bA][row][col + 1];
                     const C ym = r > 0 ? t1[r - 1][v] : lA[bA][row - 1][col];
                     const C yp = r < R - 1 ? t1[r + 1][v] : lA[bA][row + 1][col];
-                    u = as_stored(stencil_point<DT>(t1[r][v], xm, xp, ym, yp, t0[r][v], t2[r][v], c0[r][v], a),
-                                  (size_t)x + sy * y + sz * p, sr1);
+                    u = stencil_point<DT>(t1[r][v], xm, xp, ym, yp, t0[r][v], t2[r][v], c0[r][v], a);
                 }
                 u2[r][v] = u;
                 lB[bB][1 + wave * R + r][1 + lane * V + v] = u;
@@ -217,7 +207,7 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
                     const size_t i0 = (size_t)xl + sy * y + sz * p;
                     S st[V];
 #pragma unroll
-                    for (int v = 0; v < V; ++v) st[v] = Tr::store(u2[r][v], 0);   // exact: u2 is already rounded
+                    for (int v = 0; v < V; ++v) st[v] = Tr::store(u2[r][v], 0);   // FP64/FP32 only: exact
                     if (xl >= 1 && xl + V - 1 <= nx - 2) {
                         vstore<S, V>(a.Tmid + i0, st);
                     } else {
@@ -238,8 +228,7 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
                     const C xp = v < V - 1 ? y1v[v + 1] : lA[bA][ay1][col + 1];
                     const C ym = lA[bA][ay1 - 1][col];
                     const C yp = lA[bA][ay1 + 1][col];
-                    u = as_stored(stencil_point<DT>(y1v[v], xm, xp, ym, yp, y0v[v], y2v[v], ycv0[v], a),
-                                  (size_t)x + sy * yr1 + sz * p, sr1);
+                    u = stencil_point<DT>(y1v[v], xm, xp, ym, yp, y0v[v], y2v[v], ycv0[v], a);
                 }
                 lB[bB][by1][1 + lane * V + v] = u;
             }
@@ -251,8 +240,7 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
                 const C xp = lA[bA][1 + lane][ax1 + 1];
                 const C ym = lA[bA][lane][ax1];
                 const C yp = lA[bA][2 + lane][ax1];
-                u = as_stored(stencil_point<DT>(x1s, xm, xp, ym, yp, x0s, x2s, xcs0, a),
-                              (size_t)xc1 + sy * yx + sz * p, sr1);
+                u = stencil_point<DT>(x1s, xm, xp, ym, yp, x0s, x2s, xcs0, a);
             }
             lB[bB][lane][bx1] = u;
         }
@@ -279,7 +267,7 @@ __global__ __launch_bounds__(64 * NW) void step_tb2(StepArgs<DT> a, int ntx, int
                 const size_t i0 = (size_t)xl + sy * y + sz * q;
                 S st[V];
                 if constexpr (Tr::sr) {
-                    const u32x4 rb = sr_block(sr2, i0 >> 3);
+                    const u32x4 rb = sr_block(a.sr, i0 >> 3);
 #pragma unroll
                     for (int v = 0; v < V; ++v) st[v] = Tr::store(out[v], sr_word(rb, (unsigned)((i0 + v) & 7)));
                 } else {

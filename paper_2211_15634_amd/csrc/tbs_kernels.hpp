@@ -1,5 +1,5 @@
 // The S-step temporal-blocked forward kernel (S = 2..4 steps per pass over
-// HBM), bit-identical to S single steps.
+// HBM).
 #pragma once
 
 #include <type_traits>
@@ -24,8 +24,9 @@ namespace diff3d {
 // neighbours come from the level's plane staged in LDS.  Per plane iteration
 // p, level s is computed at plane p - s + 1 from level s-1 (its planes
 // p-s .. p-s+2), which is one LDS barrier per plane.
-// Intermediate levels are rounded exactly as storing them would round them,
-// so the result is bit-identical to S single steps.
+// Intermediate levels stay in the compute type (FP64 or FP32) on chip; only
+// the output level is rounded to the storage type, so FP64 and FP32 results
+// are bit-identical to S single steps and BF16 rounds once per pass.
 //
 // BF16 with round-to-nearest on 1024 threads and S >= 3 asks for eight waves
 // per SIMD (at most 64 VGPRs, two workgroups per CU; its LDS allows it): it
@@ -48,16 +49,14 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     static_assert(TX > 0 && TY > 0, "region too small for S steps");
     constexpr int K = (A0 + NTH - 1) / NTH;       // region points per thread
     __shared__ C lds[S][2][H0][W0];               // levels 0 .. S-1, double-buffered
-    // Stochastic rounding: the 64 points a wave holds for one (point slot k,
-    // level s) lie in at most 9 Philox blocks of 8 consecutive points (8 when
-    // rows start on multiples of 8: nx and TX multiples of 8), so a wave
-    // evaluates all NB*S*K blocks it needs in one Philox call (one block per
-    // lane) per plane iteration and passes the words through LDS.  Without
-    // room for them every lane draws its own block.
-    constexpr bool SR_B9 = Tr::sr && 9 * S * K <= 64;
-    constexpr bool SR_B8 = Tr::sr && !SR_B9 && 8 * S * K <= 64;
-    constexpr bool SR_BATCH = SR_B9 || SR_B8;
-    constexpr int NB = SR_B9 ? 9 : 8;
+    // Stochastic rounding of the stored level: the 64 points a wave holds
+    // for one point slot k are consecutive in x, so they lie in at most 9
+    // Philox blocks of 8 consecutive points; a wave evaluates all 9*K blocks
+    // it needs in one Philox call (one block per lane) per plane iteration
+    // and passes the words through LDS.  Without room for them every lane
+    // draws its own block.
+    constexpr int NB = 9;
+    constexpr bool SR_BATCH = Tr::sr && NB * K <= 64;
     constexpr int NWAVE = NTH / 64;
     __shared__ uint32_t srw[SR_BATCH ? NWAVE : 1][SR_BATCH ? 64 : 1][4];
 
@@ -126,14 +125,9 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     auto gidx = [&](int k, int z) __attribute__((always_inline)) {
         return (size_t)gx[k] + sy * gy[k] + sz * z;
     };
-    auto rounding = [&](size_t i, int step) __attribute__((always_inline)) -> uint32_t {
+    auto rounding = [&](size_t i) __attribute__((always_inline)) -> uint32_t {
         uint32_t rnd = 0;
-        if constexpr (Tr::sr) {
-            SrState st = a.sr;
-            st.s0 = a.sr.s0 + (uint32_t)step;
-            st.s1 = a.sr.s1 + (st.s0 < a.sr.s0 ? 1u : 0u);
-            rnd = sr_word(sr_block(st, i >> 3), (unsigned)(i & 7));
-        }
+        if constexpr (Tr::sr) rnd = sr_word(sr_block(a.sr, i >> 3), (unsigned)(i & 7));
         return rnd;
     };
     auto load_T = [&](int z, C (&dst)[K]) __attribute__((always_inline)) {
@@ -191,42 +185,29 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     load_Ci(p0 + 1, lc[0]);
     stage(0, 1, t0[1]);                     // plane p0 is read as "the previous iteration's" buffer
 
-    // One plane iteration; PAR = (p - p0) & 1 selects the load slots.
-    // random words of this iteration's roundings (level s, slot k)
-    uint32_t rnd[SR_BATCH ? S : 1][SR_BATCH ? K : 1];
-    const bool batched = SR_B9 || (SR_B8 && nx % 8 == 0 && TX % 8 == 0);
+    // random words of this iteration's stored points (slot k)
+    uint32_t rnd[SR_BATCH ? K : 1];
     auto draw = [&](int p) __attribute__((always_inline)) {
         if constexpr (SR_BATCH) {
-            if (!batched) return;
             const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
-            // first block of each (s, k): from lane 0's point (wave-uniform)
-            size_t g0[S][K];
+            const int z = p - S + 1;             // the plane level S reaches in this iteration
+            // first block of each slot: from lane 0's point (wave-uniform)
+            size_t g0[K];
 #pragma unroll
-            for (int s = 1; s <= S; ++s)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const size_t g = gidx(k, p - s + 1) >> 3;
-                    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)g);
-                    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(g >> 32));
-                    g0[s - 1][k] = ((size_t)hi << 32) | lo;
-                }
-            // lane L computes block b of (s, k), L = ((s-1)*K + k)*NB + b
-            if (lane < NB * S * K) {
-                const int sk = lane / NB, b = lane % NB;
+            for (int k = 0; k < K; ++k) {
+                const size_t g = gidx(k, z) >> 3;
+                const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)g);
+                const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(g >> 32));
+                g0[k] = ((size_t)hi << 32) | lo;
+            }
+            // lane L computes block b of slot k, L = k*NB + b
+            if (lane < NB * K) {
+                const int kk = lane / NB, b = lane % NB;
                 size_t g = 0;
-                int step = 0;
 #pragma unroll
-                for (int s = 1; s <= S; ++s)
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-                        if (sk == (s - 1) * K + k) {
-                            g = g0[s - 1][k] + (size_t)b;
-                            step = s - 1;
-                        }
-                SrState st = a.sr;
-                st.s0 = a.sr.s0 + (uint32_t)step;
-                st.s1 = a.sr.s1 + (st.s0 < a.sr.s0 ? 1u : 0u);
-                const u32x4 r = sr_block(st, g);
+                for (int k = 0; k < K; ++k)
+                    if (kk == k) g = g0[k] + (size_t)b;
+                const u32x4 r = sr_block(a.sr, g);
                 srw[wv][lane][0] = r.x;
                 srw[wv][lane][1] = r.y;
                 srw[wv][lane][2] = r.z;
@@ -234,25 +215,24 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
             }
             __builtin_amdgcn_wave_barrier();   // the wave's LDS writes precede its reads (in order per wave)
 #pragma unroll
-            for (int s = 1; s <= S; ++s)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const size_t i = gidx(k, p - s + 1);
-                    const int b = min(max((int)((i >> 3) - g0[s - 1][k]), 0), NB - 1);
-                    const unsigned j = (unsigned)(i & 7);
-                    const uint32_t w = srw[wv][((s - 1) * K + k) * NB + b][j >> 1];
-                    rnd[s - 1][k] = (j & 1) ? (w & 0xFFFF0000u) : (w << 16);
-                }
+            for (int k = 0; k < K; ++k) {
+                const size_t i = gidx(k, z);
+                const int b = min(max((int)((i >> 3) - g0[k]), 0), NB - 1);
+                const unsigned j = (unsigned)(i & 7);
+                const uint32_t w = srw[wv][k * NB + b][j >> 1];
+                rnd[k] = (j & 1) ? (w & 0xFFFF0000u) : (w << 16);
+            }
             __builtin_amdgcn_wave_barrier();
         }
     };
-    auto rounding_at = [&](int k, int s, int z) __attribute__((always_inline)) -> uint32_t {
+    auto rounding_at = [&](int k, int z) __attribute__((always_inline)) -> uint32_t {
         if constexpr (SR_BATCH)
-            return batched ? rnd[s - 1][k] : rounding(gidx(k, z), s - 1);
+            return rnd[k];
         else
-            return rounding(gidx(k, z), s - 1);
+            return rounding(gidx(k, z));
     };
 
+    // One plane iteration; PAR = (p - p0) & 1 selects the load slots.
     auto iteration = [&](auto par, int p) __attribute__((always_inline)) {
         constexpr int PAR = decltype(par)::value;
         constexpr int buf = PAR, rbuf = PAR ^ 1;
@@ -286,11 +266,11 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
                     const C yp = lds[s - 1][rbuf][rr[k] + 1][cc[k]];
                     const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, ci[s][k], a);
                     if (s < S) {
-                        v = Tr::load(Tr::store(w, rounding_at(k, s, z)));
+                        v = w;
                     } else if (z >= zb && z < ze &&
                                (kMaskTable ? otile[k]
                                            : gx[k] >= ox0 && gx[k] < ox1 && gy[k] >= oy0 && gy[k] < oy1)) {
-                        const S_ o = Tr::store(w, rounding_at(k, S, z));
+                        const S_ o = Tr::store(w, rounding_at(k, z));
                         if (NT)
                             __builtin_nontemporal_store(o, a.T2 + gidx(k, z));
                         else

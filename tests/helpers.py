@@ -1,5 +1,6 @@
-"""Shared test helpers: moving seeded numpy fields to the GPU, sub-box
-oracle evaluation at sampled points, and error measures."""
+"""Shared test helpers: moving seeded numpy fields to the GPU, the stored
+(FP32/BF16) form of a field for the emulator, sub-box oracle evaluation at
+sampled points, and error measures."""
 from __future__ import annotations
 
 import numpy as np
@@ -8,8 +9,53 @@ import oracle
 
 
 def to_dev(a: np.ndarray, dtype):
+    """A numpy FP64 field on the GPU in `dtype`, rounded on the CPU (so the
+    emulator can be given the very same stored values, see stored())."""
     import torch
-    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dtype).contiguous().to("cuda")
+
+
+def stored(a: np.ndarray, dtype) -> np.ndarray:
+    """The stored values to_dev puts on the GPU, as the emulator takes them:
+    float32, or BF16 bits as uint16."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dtype).contiguous()
+    if dtype == torch.bfloat16:
+        return t.view(torch.int16).numpy().view(np.uint16).copy()
+    if dtype == torch.float32:
+        return t.numpy().copy()
+    raise ValueError("stored() is for the reduced-precision forms")
+
+
+def bits(t) -> np.ndarray:
+    """A GPU tensor's stored values for comparison with the emulator."""
+    import torch
+    h = t.detach().cpu().contiguous()
+    if h.dtype == torch.bfloat16:
+        return h.view(torch.int16).numpy().view(np.uint16)
+    return h.numpy()
+
+
+def storage_code(dtype, rounding="sr") -> int:
+    import torch
+    if dtype == torch.float32:
+        return oracle.ST_F32
+    if dtype == torch.bfloat16:
+        return oracle.ST_BF16_SR if rounding == "sr" else oracle.ST_BF16_RNE
+    raise ValueError(dtype)
+
+
+def emulate_run(lib, T0, Ci, s, nt, dtype, rounding="sr", cfg=None, ckpt_every=0, T0s=None):
+    """The emulator's result for lib.run with the same arguments: the pass
+    lengths the library's host logic takes for them (lib.pass_plan), each
+    pass in FP32 and its final state stored (and rounded).  T0s: stored
+    initial values if they are not those of to_dev(T0)."""
+    passes = lib.pass_plan(T0.shape, nt, dtype, ckpt_every=ckpt_every, rounding=rounding, cfg=cfg)
+    seed = cfg.sr_seed if cfg is not None else 0
+    step0 = cfg.sr_step if cfg is not None else 0
+    a = stored(T0, dtype) if T0s is None else T0s
+    return oracle.emulate_forward(a, stored(Ci, dtype), s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], passes,
+                                  storage_code(dtype, rounding), seed=seed, step0=step0)
 
 
 def to_host(t) -> np.ndarray:

@@ -73,19 +73,32 @@ def test_philox_known_answers():
 
 
 def test_workspace_bytes():
+    W = d3._lib.diff3d_adjoint_workspace_bytes
     f = 64 * 64 * 64 * 8
-    # nt=200, C=14: 15 checkpoints (14 stored), 13 recompute fields, 1 ping-pong
-    assert d3._lib.diff3d_adjoint_workspace_bytes(64, 64, 64, 200, 14, d3.F64) == (14 + 13 + 1) * f
-    # nt=500, C=32 at 1024^3 FP32: 16 checkpoints
+    # nt=200, C=14, fused three-step passes: 15 checkpoints (14 stored), the
+    # starts of passes 2..5 of a segment (2, 3, 3, 3, 3 steps): 4 fields, 1 ping-pong
+    assert W(64, 64, 64, 200, 14, d3.F64, None) == (14 + 4 + 1) * f
+    # every state of a segment with single-step or two-step adjoint kernels
+    for k in (d3.KERNEL_NAIVE, d3.KERNEL_ZMARCH, d3.KERNEL_TB2):
+        assert W(64, 64, 64, 200, 14, d3.F64, d3._ccfg(d3.Config(kernel=k))) == (14 + 13 + 1) * f
+    # two-step fused passes: 7 passes per segment, 6 recomputed starts
+    c2 = d3._ccfg(d3.Config(kernel=d3.KERNEL_TBS, pass_steps=2))
+    assert W(64, 64, 64, 200, 14, d3.F64, c2) == (14 + 6 + 1) * f
+    # nt=500, C=32 at 1024^3 FP32: 16 checkpoints, 10 recomputed starts (11 passes)
     g = 1024 ** 3 * 4
-    assert d3._lib.diff3d_adjoint_workspace_bytes(1024, 1024, 1024, 500, 32, d3.F32) == (15 + 31 + 1) * g
-    assert d3._lib.diff3d_adjoint_workspace_bytes(64, 64, 64, 0, 14, d3.F64) == 14 * f
-    assert d3._lib.diff3d_adjoint_workspace_bytes(64, 64, 64, 10, 0, d3.F64) == 0
-    assert d3._lib.diff3d_adjoint_workspace_bytes(2, 64, 64, 10, 3, d3.F64) == 0
-    assert d3._lib.diff3d_adjoint_workspace_bytes(64, 64, 64, 10, 3, 9) == 0
+    assert W(1024, 1024, 1024, 500, 32, d3.F32, None) == (15 + 10 + 1) * g
+    # a checkpoint interval longer than the run: one segment of nt steps
+    assert W(64, 64, 64, 5, 14, d3.F64, None) == (0 + 1 + 1) * f
+    assert W(64, 64, 64, 5, 14, d3.F64, d3._ccfg(d3.Config(kernel=d3.KERNEL_ZMARCH))) == (0 + 4 + 1) * f
+    assert W(64, 64, 64, 0, 14, d3.F64, None) == 1 * f
+    assert W(64, 64, 64, 10, 0, d3.F64, None) == 0
+    assert W(2, 64, 64, 10, 3, d3.F64, None) == 0
+    assert W(64, 64, 64, 10, 3, 9, None) == 0
     # ragged field sizes are padded to 256-byte boundaries
     r = 5 * 6 * 7 * 4
-    assert d3._lib.diff3d_adjoint_workspace_bytes(5, 6, 7, 10, 3, d3.F32) == (3 + 2 + 1) * ((r + 255) // 256 * 256)
+    assert W(5, 6, 7, 10, 3, d3.F32, None) == (3 + 0 + 1) * ((r + 255) // 256 * 256)
+    assert W(5, 6, 7, 10, 3, d3.F32, d3._ccfg(d3.Config(kernel=d3.KERNEL_ZMARCH))) == \
+        (3 + 2 + 1) * ((r + 255) // 256 * 256)
 
 
 # Host-side validation: every call below must be rejected before any HIP
@@ -98,82 +111,158 @@ A, B, Cc = P(0x10000000), P(0x20000000), P(0x30000000)
 def test_step_validation():
     L = d3._lib
     args = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
-    assert L.diff3d_step(None, B, Cc, *args, d3.F64, None) == d3.EINVAL
-    assert L.diff3d_step(A, None, Cc, *args, d3.F64, None) == d3.EINVAL
-    assert L.diff3d_step(A, B, None, *args, d3.F64, None) == d3.EINVAL
-    assert L.diff3d_step(A, B, Cc, *args, 7, None) == d3.EDTYPE
-    assert L.diff3d_step(A, B, Cc, *args, -1, None) == d3.EDTYPE
-    assert L.diff3d_step(A, A, Cc, *args, d3.F64, None) == d3.EINVAL      # T2 aliases T
-    assert L.diff3d_step(A, B, A, *args, d3.F64, None) == d3.EINVAL       # T2 aliases Ci
+    assert L.diff3d_step(None, B, Cc, *args, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_step(A, None, Cc, *args, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_step(A, B, None, *args, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_step(A, B, Cc, *args, 7, None, None) == d3.EDTYPE
+    assert L.diff3d_step(A, B, Cc, *args, -1, None, None) == d3.EDTYPE
+    assert L.diff3d_step(A, A, Cc, *args, d3.F64, None, None) == d3.EINVAL      # T2 aliases T
+    assert L.diff3d_step(A, B, A, *args, d3.F64, None, None) == d3.EINVAL       # T2 aliases Ci
     # T2 overlapping the tail of T
     near = P(0x20000000 + 64 * 64 * 64 * 8 - 8)
-    assert L.diff3d_step(near, B, Cc, *args, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_step(near, B, Cc, *args, d3.F64, None, None) == d3.EINVAL
     for bad in ((2, 64, 64), (64, 2, 64), (64, 64, 2), (0, 5, 5), (-5, 5, 5)):
-        assert L.diff3d_step(A, B, Cc, *bad, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F64, None) == d3.EINVAL
+        assert L.diff3d_step(A, B, Cc, *bad, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F64, None, None) == d3.EINVAL
     # more than 2^40 points
-    assert L.diff3d_step(A, B, Cc, 1 << 14, 1 << 14, 1 << 14, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F32, None) == d3.EINVAL
+    assert L.diff3d_step(A, B, Cc, 1 << 14, 1 << 14, 1 << 14, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F32, None, None) == d3.EINVAL
 
 
 def test_step2_validation():
     L = d3._lib
     args = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
-    assert L.diff3d_step2(None, B, Cc, *args, d3.F64, None) == d3.EINVAL
-    assert L.diff3d_step2(A, A, Cc, *args, d3.F64, None) == d3.EINVAL
-    assert L.diff3d_step2(A, B, A, *args, d3.F32, None) == d3.EINVAL
-    assert L.diff3d_step2(A, B, Cc, *args, 4, None) == d3.EDTYPE
-    assert L.diff3d_step2(A, B, Cc, 64, 2, 64, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_step2(None, B, Cc, *args, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_step2(A, A, Cc, *args, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_step2(A, B, A, *args, d3.F32, None, None) == d3.EINVAL
+    assert L.diff3d_step2(A, B, Cc, *args, 4, None, None) == d3.EDTYPE
+    assert L.diff3d_step2(A, B, Cc, 64, 2, 64, 1.0, 1e-5, 1.0, 1.0, 1.0, d3.F64, None, None) == d3.EINVAL
 
 
 def test_stepn_validation():
     L = d3._lib
     args = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
     for bad_n in (0, -1, d3.MAX_PASS_STEPS + 1):
-        assert L.diff3d_stepn(A, B, Cc, *args, bad_n, d3.F64, None) == d3.EINVAL
-    assert L.diff3d_stepn(None, B, Cc, *args, 3, d3.F64, None) == d3.EINVAL
-    assert L.diff3d_stepn(A, A, Cc, *args, 3, d3.F64, None) == d3.EINVAL
-    assert L.diff3d_stepn(A, B, A, *args, 4, d3.F32, None) == d3.EINVAL
-    assert L.diff3d_stepn(A, B, Cc, *args, 3, 4, None) == d3.EDTYPE
-    assert L.diff3d_stepn(A, B, Cc, 64, 64, 2, 1.0, 1e-5, 1.0, 1.0, 1.0, 3, d3.F64, None) == d3.EINVAL
+        assert L.diff3d_stepn(A, B, Cc, *args, bad_n, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_stepn(None, B, Cc, *args, 3, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_stepn(A, A, Cc, *args, 3, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_stepn(A, B, A, *args, 4, d3.F32, None, None) == d3.EINVAL
+    assert L.diff3d_stepn(A, B, Cc, *args, 3, 4, None, None) == d3.EDTYPE
+    assert L.diff3d_stepn(A, B, Cc, 64, 64, 2, 1.0, 1e-5, 1.0, 1.0, 1.0, 3, d3.F64, None, None) == d3.EINVAL
 
 
-def test_pass_steps_setting():
+def _plan(shape, nt, dtype, C=0, cfg=None):
+    return d3.pass_plan(shape, nt, dtype, ckpt_every=C, cfg=cfg)
+
+
+def test_config_validation():
+    """Bad configurations are rejected before anything is enqueued (the fake
+    pointers below are never dereferenced)."""
     L = d3._lib
-    for bad in (-1, 1, d3.MAX_PASS_STEPS + 1):
-        assert L.diff3d_set_pass_steps(bad) == d3.EINVAL
-    for good in range(2, d3.MAX_PASS_STEPS + 1):
-        assert L.diff3d_set_pass_steps(good) == d3.OK
-    assert L.diff3d_set_pass_steps(0) == d3.OK
+    args = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
+    bad = [d3.Config(kernel=17), d3.Config(kernel=-1), d3.Config(pass_steps=1), d3.Config(pass_steps=5),
+           d3.Config(zmarch=d3.Tile(p=(3, 4, 4, 0))),                  # not instantiated
+           d3.Config(zmarch=d3.Tile(steps=2, p=(2, 4, 4, 1))),         # steps only for S-step / reverse
+           d3.Config(zmarch=d3.Tile(zlen=-1)),
+           d3.Config(tb2=d3.Tile(p=(9, 9, 9, 9))),
+           d3.Config(tbs=d3.Tile(p=(64, 32, 1024, 0))),               # an S-step override names its pass length
+           d3.Config(tbs=d3.Tile(steps=4, p=(64, 33, 1024, 0))),
+           d3.Config(tbs=d3.Tile(steps=5)),
+           d3.Config(tbs=d3.Tile(steps=2, p=(64, 16, 512, 1), zlen=-3))]
+    for c in bad:
+        assert L.diff3d_step(A, B, Cc, *args, d3.F64, None, d3._ccfg(c)) == d3.EINVAL, c
+        assert L.diff3d_run(A, B, Cc, *args, 10, d3.F64, None, None, 0, d3._ccfg(c)) == d3.EINVAL, c
+        assert L.diff3d_pass_plan(64, 64, 64, 10, 0, d3.F64, d3._ccfg(c), None, 0) == d3.EINVAL, c
+    # fields the Python Config cannot express wrongly, set on the raw struct
+    for field, value in (("narrow", 2), ("reserved", 1)):
+        raw = d3._CConfig()
+        setattr(raw, field, value)
+        assert L.diff3d_step(A, B, Cc, *args, d3.F64, None, ctypes.byref(raw)) == d3.EINVAL
+        assert L.diff3d_pass_plan(64, 64, 64, 10, 0, d3.F64, ctypes.byref(raw), None, 0) == d3.EINVAL
+    # the same override is instantiated for one storage size and not another
+    c = d3.Config(zmarch=d3.Tile(p=(1, 8, 4, 0)))
+    assert L.diff3d_pass_plan(64, 64, 64, 10, 0, d3.F64, d3._ccfg(c), None, 0) == 3
+    assert L.diff3d_pass_plan(64, 64, 64, 10, 0, d3.F32, d3._ccfg(c), None, 0) == d3.EINVAL
+    # reverse-only overrides: checked where they are used
+    for c in (d3.Config(adj=d3.Tile(p=(3, 3, 3, 0))), d3.Config(rev=d3.Tile(p=(64, 16, 1024, 0))),
+              d3.Config(rev=d3.Tile(steps=4, p=(64, 16, 1024, 0))), d3.Config(adj2=d3.Tile(steps=2))):
+        assert L.diff3d_adjoint_workspace_bytes(32, 32, 32, 20, 5, d3.F64, d3._ccfg(c)) == 0, c
+    assert L.diff3d_adjoint_workspace_bytes(32, 32, 32, 20, 5, d3.F64,
+                                            d3._ccfg(d3.Config(rev=d3.Tile(steps=3, p=(64, 16, 512, 0))))) > 0
+
+
+def test_pass_plan_rules():
+    """The time loop's pass lengths follow the documented rule, recomputed
+    here independently: passes of at most S steps that never cross a
+    checkpointed state; near-equal lengths per stretch by default, exact
+    lengths (and a shorter last one) when a pass length is set."""
+    import torch
+
+    def expect(nt, C, S, even):
+        out, it = [], 0
+        stops = sorted({k for k in range(C, nt, C)} if C else set()) + [nt]
+        for stop in stops:
+            rem = stop - it
+            if rem == 0:
+                continue
+            if even:
+                m = -(-rem // S)
+                base, extra = divmod(rem, m)
+                out += [base + 1] * extra + [base] * (m - extra)
+            else:
+                out += [S] * (rem // S) + ([rem % S] if rem % S else [])
+            it = stop
+        return out
+
+    f64 = torch.float64
+    assert _plan((512, 512, 512), 100, f64) == [4] * 25
+    assert _plan((256, 256, 256), 200, f64, C=14) == expect(200, 14, 4, True)
+    assert _plan((256, 256, 256), 200, f64, C=14)[:4] == [4, 4, 3, 3]
+    for nt, C in ((0, 0), (1, 0), (7, 0), (31, 7), (30, 14), (9, 4), (5, 1), (8, 8), (23, 5)):
+        for S in (2, 3, 4):
+            cfg = d3.Config(kernel=d3.KERNEL_TBS, pass_steps=S)
+            assert _plan((9, 9, 9), nt, f64, C, cfg) == expect(nt, C, S, False), (nt, C, S)
+            assert sum(_plan((9, 9, 9), nt, f64, C, cfg)) == nt
+        assert _plan((9, 9, 9), nt, f64, C) == expect(nt, C, 4, True), (nt, C)
+        assert _plan((9, 9, 9), nt, f64, C, d3.Config(kernel=d3.KERNEL_ZMARCH)) == [1] * nt
+        assert _plan((9, 9, 9), nt, f64, C, d3.Config(kernel=d3.KERNEL_TB2)) == expect(nt, C, 2, True)
+    # FP32 takes three-step passes on planes above 768^2 points
+    assert set(_plan((4, 769, 768), 12, torch.float32)) == {3}
+    assert set(_plan((4, 768, 768), 12, torch.float32)) == {4}
+    L = d3._lib
+    assert L.diff3d_pass_plan(9, 9, 9, -1, 0, d3.F64, None, None, 0) == d3.EINVAL
+    assert L.diff3d_pass_plan(9, 9, 9, 5, -1, d3.F64, None, None, 0) == d3.EINVAL
+    assert L.diff3d_pass_plan(9, 9, 9, 5, 0, 7, None, None, 0) == d3.EDTYPE
+    assert L.diff3d_pass_plan(2, 9, 9, 5, 0, d3.F64, None, None, 0) == d3.EINVAL
 
 
 def test_run_validation():
     L = d3._lib
     g = (64, 64, 64, 1.0, 1e-5, 63.0, 63.0, 63.0)
-    assert L.diff3d_run(A, B, Cc, *g, -1, d3.F64, None, None, 0) == d3.EINVAL
-    assert L.diff3d_run(A, B, Cc, *g, 10, 5, None, None, 0) == d3.EDTYPE
-    assert L.diff3d_run(A, A, Cc, *g, 10, d3.F64, None, None, 0) == d3.EINVAL
-    assert L.diff3d_run(A, B, A, *g, 10, d3.F64, None, None, 0) == d3.EINVAL
-    assert L.diff3d_run(A, B, Cc, *g, 10, d3.F64, None, P(0x40000000), 0) == d3.EINVAL  # ckpt without C
-    assert L.diff3d_run(A, B, Cc, *g, 30, d3.F64, None, A, 10) == d3.EINVAL             # ckpt over T
-    assert L.diff3d_run(A, B, Cc, *g, 0, d3.F64, None, None, 0) == d3.OK                # nt=0: no-op
+    assert L.diff3d_run(A, B, Cc, *g, -1, d3.F64, None, None, 0, None) == d3.EINVAL
+    assert L.diff3d_run(A, B, Cc, *g, 10, 5, None, None, 0, None) == d3.EDTYPE
+    assert L.diff3d_run(A, A, Cc, *g, 10, d3.F64, None, None, 0, None) == d3.EINVAL
+    assert L.diff3d_run(A, B, A, *g, 10, d3.F64, None, None, 0, None) == d3.EINVAL
+    assert L.diff3d_run(A, B, Cc, *g, 10, d3.F64, None, P(0x40000000), 0, None) == d3.EINVAL  # ckpt without C
+    assert L.diff3d_run(A, B, Cc, *g, 30, d3.F64, None, A, 10, None) == d3.EINVAL             # ckpt over T
+    assert L.diff3d_run(A, B, Cc, *g, 0, d3.F64, None, None, 0, None) == d3.OK                # nt=0: no-op
 
 
 def test_adjoint_validation():
     L = d3._lib
     W = P(0x50000000)
     n = 32 * 32 * 32 * 8
-    ws = L.diff3d_adjoint_workspace_bytes(32, 32, 32, 20, 5, d3.F64)
+    ws = L.diff3d_adjoint_workspace_bytes(32, 32, 32, 20, 5, d3.F64, None)
     g = (32, 32, 32, 1.0, 1e-4, 31.0, 31.0, 31.0, 20, 5)
     D, E = P(0x60000000), P(0x70000000)
-    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws, 0, *g, d3.BF16, None) == d3.EDTYPE
-    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws, 0, *g, 9, None) == d3.EDTYPE
-    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws - 1, 0, *g, d3.F64, None) == d3.EWORKSPACE
-    assert L.diff3d_adjoint_run(A, B, Cc, D, E, None, ws, 0, *g, d3.F64, None) == d3.EWORKSPACE
-    assert L.diff3d_adjoint_run(A, B, Cc, D, D, W, ws, 0, *g, d3.F64, None) == d3.EINVAL   # gT0 == gCi
-    assert L.diff3d_adjoint_run(A, B, Cc, A, E, W, ws, 0, *g, d3.F64, None) == d3.EINVAL   # gT0 == T0
-    assert L.diff3d_adjoint_run(A, B, Cc, D, E, P(0x60000000 + n // 2), ws, 0, *g, d3.F64, None) == d3.EINVAL
-    assert L.diff3d_adjoint_run(None, B, Cc, D, E, W, ws, 0, *g, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws, 0, *g, d3.BF16, None, None) == d3.EDTYPE
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws, 0, *g, 9, None, None) == d3.EDTYPE
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws - 1, 0, *g, d3.F64, None, None) == d3.EWORKSPACE
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, None, ws, 0, *g, d3.F64, None, None) == d3.EWORKSPACE
+    assert L.diff3d_adjoint_run(A, B, Cc, D, D, W, ws, 0, *g, d3.F64, None, None) == d3.EINVAL   # gT0 == gCi
+    assert L.diff3d_adjoint_run(A, B, Cc, A, E, W, ws, 0, *g, d3.F64, None, None) == d3.EINVAL   # gT0 == T0
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, P(0x60000000 + n // 2), ws, 0, *g, d3.F64, None, None) == d3.EINVAL
+    assert L.diff3d_adjoint_run(None, B, Cc, D, E, W, ws, 0, *g, d3.F64, None, None) == d3.EINVAL
     bad = (32, 32, 32, 1.0, 1e-4, 31.0, 31.0, 31.0, 20, 0)
-    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws, 0, *bad, d3.F64, None) == d3.EINVAL
+    assert L.diff3d_adjoint_run(A, B, Cc, D, E, W, ws, 0, *bad, d3.F64, None, None) == d3.EINVAL
 
 
 def test_reduction_and_copy_validation():
@@ -190,16 +279,17 @@ def test_reduction_and_copy_validation():
     assert L.diff3d_copy(A, B, 0, None) == d3.OK
 
 
-def test_kernel_selection_roundtrip():
-    old = d3.get_kernel()
-    try:
-        for k in (d3.KERNEL_NAIVE, d3.KERNEL_ZMARCH, d3.KERNEL_TB2, d3.KERNEL_TBS, d3.KERNEL_AUTO):
-            d3.set_kernel(k)
-            assert d3.get_kernel() == k
-        with pytest.raises(d3.Diff3dError):
-            d3.set_kernel(17)
-    finally:
-        d3.set_kernel(old)
+def test_no_process_state():
+    """The library exports no setter: everything a call depends on is an
+    argument, and the product path reads no environment variable."""
+    lib = ctypes.CDLL(d3.LIB_PATH)
+    for name in ("diff3d_set_kernel", "diff3d_get_kernel", "diff3d_set_pass_steps", "diff3d_set_sr_seed"):
+        assert not hasattr(lib, name), name
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from helpers import csrc_text
+    src = csrc_text()
+    assert "getenv" not in src and "environ" not in src
 
 
 def test_default_tile_configurations_are_instantiated():

@@ -1,28 +1,19 @@
 """Checkpointed reverse sweep on the GPU: against the oracle's FP64 reverse
-sweep (bit for bit: same operation order), central finite differences,
-the dot-product identity and the sine-mode closed form at full size."""
+sweep (bit for bit: same operation order) and its FP32 emulation, central
+finite differences, the dot-product identity and the sine-mode closed form
+at full size."""
 import math
-import os
 
 import numpy as np
 import pytest
 
 import oracle
 import workloads
-from helpers import instantiated_configs, norm_rel, oracle_reverse_at, sample_points, to_dev, to_host
+from helpers import instantiated_configs, norm_rel, oracle_reverse_at, sample_points, stored, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-
-
-@pytest.fixture(autouse=True)
-def _reset(lib):
-    lib.set_kernel(lib.KERNEL_AUTO)
-    yield
-    lib.set_kernel(lib.KERNEL_AUTO)
-    for k in ("DIFF3D_AZLEN", "DIFF3D_ACFG", "DIFF3D_BZLEN", "DIFF3D_BCFG"):
-        os.environ.pop(k, None)
 
 
 def _inputs(shape, seed=0):
@@ -35,32 +26,47 @@ def _inputs(shape, seed=0):
     return T0, Ci, g, s
 
 
-def _adjoint(lib, T0, Ci, g, s, nt, C, dtype=torch.float64, ready=False):
+def _sc(s):
+    return (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+
+
+def _adjoint(lib, T0, Ci, g, s, nt, C, dtype=torch.float64, ready=False, cfg=None):
     T0d, Cid, gd = to_dev(T0, dtype), to_dev(Ci, dtype), to_dev(g, dtype)
-    ws = torch.empty(lib.adjoint_workspace_bytes(T0.shape, nt, C, dtype), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.adjoint_workspace_bytes(T0.shape, nt, C, dtype, cfg), dtype=torch.uint8, device="cuda")
     if ready:
         T = T0d.clone()
-        lib.run(T, torch.empty_like(T), Cid, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt, ckpt=ws,
-                ckpt_every=C)
+        lib.run(T, torch.empty_like(T), Cid, *_sc(s), nt, ckpt=ws, ckpt_every=C, cfg=cfg)
     gT0 = torch.empty_like(T0d)
     gCi = torch.empty_like(T0d)
-    lib.adjoint_run(T0d, Cid, gd, gT0, gCi, ws, ready, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt, C)
+    lib.adjoint_run(T0d, Cid, gd, gT0, gCi, ws, ready, *_sc(s), nt, C, cfg=cfg)
     torch.cuda.synchronize()
     return to_host(gT0), to_host(gCi)
+
+
+def _emulated32(T0, Ci, g, s, nt):
+    """The oracle's FP32 reverse sweep on the FP32 inputs the GPU gets."""
+    f32 = lambda a: stored(a, torch.float32)
+    a, b = oracle.emulate_reverse32(f32(T0), f32(Ci), f32(g), *_sc(s), nt)
+    return a.astype(np.float64), b.astype(np.float64)
 
 
 @pytest.mark.parametrize("shape,nt,C", [((6, 5, 7), 5, 2), ((19, 37, 131), 9, 4), ((21, 20, 128), 13, 5),
                                         ((3, 3, 3), 4, 3), ((8, 70, 64), 7, 1), ((9, 9, 192), 6, 10)])
 @pytest.mark.parametrize("kernel", ["naive", "zmarch", "tb2", "auto"])
 def test_fp64_matches_oracle_bitwise(lib, shape, nt, C, kernel):
-    lib.set_kernel({"naive": lib.KERNEL_NAIVE, "zmarch": lib.KERNEL_ZMARCH, "tb2": lib.KERNEL_TB2,
-                    "auto": lib.KERNEL_AUTO}[kernel])
+    c = lib.Config(kernel={"naive": lib.KERNEL_NAIVE, "zmarch": lib.KERNEL_ZMARCH, "tb2": lib.KERNEL_TB2,
+                           "auto": lib.KERNEL_AUTO}[kernel])
     T0, Ci, g, s = _inputs(shape)
-    rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
+    rT0, rCi = oracle.reverse(T0, Ci, g, *_sc(s), nt)
     for ready in (False, True):
-        gT0, gCi = _adjoint(lib, T0, Ci, g, s, nt, C, ready=ready)
+        gT0, gCi = _adjoint(lib, T0, Ci, g, s, nt, C, ready=ready, cfg=c)
         np.testing.assert_array_equal(gT0, rT0)
         np.testing.assert_array_equal(gCi, rCi)
+    # FP32: the oracle's FP32 emulation, bit for bit
+    eT0, eCi = _emulated32(T0, Ci, g, s, nt)
+    gT0, gCi = _adjoint(lib, T0, Ci, g, s, nt, C, dtype=torch.float32, ready=True, cfg=c)
+    np.testing.assert_array_equal(gT0, eT0)
+    np.testing.assert_array_equal(gCi, eCi)
 
 
 def _adj_cases():
@@ -75,18 +81,15 @@ def _adj_cases():
 @pytest.mark.parametrize("dtype,cfg,azlen", _adj_cases())
 def test_adjoint_configs(lib, dtype, cfg, azlen):
     """Every instantiated adjoint configuration and several z-chunk lengths:
-    FP64 bit-identical to the oracle, FP32 bit-identical to the naive kernel."""
-    os.environ["DIFF3D_AZLEN"] = str(azlen)
-    os.environ["DIFF3D_ACFG"] = ",".join(str(c) for c in cfg)
-    lib.set_kernel(lib.KERNEL_ZMARCH)
+    FP64 bit-identical to the oracle, FP32 to its FP32 emulation."""
+    c = lib.Config(kernel=lib.KERNEL_ZMARCH, adj=lib.Tile(p=tuple(cfg) + (0,), zlen=azlen))
     T0, Ci, g, s = _inputs((11, 23, 128), seed=azlen + sum(cfg))
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    gT0, gCi = _adjoint(lib, T0, Ci, g, s, 5, 3, dtype=tdt)
+    gT0, gCi = _adjoint(lib, T0, Ci, g, s, 5, 3, dtype=tdt, cfg=c)
     if dtype == "f64":
-        rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 5)
+        rT0, rCi = oracle.reverse(T0, Ci, g, *_sc(s), 5)
     else:
-        lib.set_kernel(lib.KERNEL_NAIVE)
-        rT0, rCi = _adjoint(lib, T0, Ci, g, s, 5, 3, dtype=tdt)
+        rT0, rCi = _emulated32(T0, Ci, g, s, 5)
     np.testing.assert_array_equal(gT0, rT0)
     np.testing.assert_array_equal(gCi, rCi)
 
@@ -103,31 +106,26 @@ def _adj2_cases():
 @pytest.mark.parametrize("dtype,cfg,zlen", _adj2_cases())
 def test_adjoint_two_step_configs(lib, dtype, cfg, zlen):
     """Every instantiated two-step adjoint configuration and several z-chunk
-    lengths: FP64 bit-identical to the oracle, FP32 bit-identical to single
-    adjoint steps of the naive kernel."""
-    os.environ["DIFF3D_BZLEN"] = str(zlen)
-    os.environ["DIFF3D_BCFG"] = ",".join(str(c) for c in cfg)
-    lib.set_kernel(lib.KERNEL_TB2)
+    lengths: FP64 bit-identical to the oracle, FP32 to its FP32 emulation."""
+    c = lib.Config(kernel=lib.KERNEL_TB2, adj2=lib.Tile(p=tuple(cfg) + (0,), zlen=zlen))
     T0, Ci, g, s = _inputs((13, 21, 128), seed=zlen + sum(cfg) + 7)
     tdt = torch.float64 if dtype == "f64" else torch.float32
-    gT0, gCi = _adjoint(lib, T0, Ci, g, s, 9, 4, dtype=tdt)
+    gT0, gCi = _adjoint(lib, T0, Ci, g, s, 9, 4, dtype=tdt, cfg=c)
     if dtype == "f64":
-        rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], 9)
+        rT0, rCi = oracle.reverse(T0, Ci, g, *_sc(s), 9)
     else:
-        lib.set_kernel(lib.KERNEL_NAIVE)
-        rT0, rCi = _adjoint(lib, T0, Ci, g, s, 9, 4, dtype=tdt)
+        rT0, rCi = _emulated32(T0, Ci, g, s, 9)
     np.testing.assert_array_equal(gT0, rT0)
     np.testing.assert_array_equal(gCi, rCi)
 
 
 @pytest.mark.parametrize("shape", [(3, 3, 3), (4, 5, 6), (5, 70, 33), (9, 3, 130), (6, 66, 64)])
 def test_adjoint_two_step_small_and_ragged(lib, shape):
-    os.environ["DIFF3D_BZLEN"] = "1"
-    lib.set_kernel(lib.KERNEL_TB2)
+    c = lib.Config(kernel=lib.KERNEL_TB2, adj2=lib.Tile(zlen=1), tb2=lib.Tile(zlen=1))
     T0, Ci, g, s = _inputs(shape, seed=11)
     for nt, C in ((2, 2), (5, 3), (8, 8)):
-        rT0, rCi = oracle.reverse(T0, Ci, g, s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"], nt)
-        gT0, gCi = _adjoint(lib, T0, Ci, g, s, nt, C)
+        rT0, rCi = oracle.reverse(T0, Ci, g, *_sc(s), nt)
+        gT0, gCi = _adjoint(lib, T0, Ci, g, s, nt, C, cfg=c)
         np.testing.assert_array_equal(gT0, rT0)
         np.testing.assert_array_equal(gCi, rCi)
 
@@ -231,6 +229,9 @@ def test_fp32_against_fp64_oracle(lib):
     e0, e1 = norm_rel(gT0, rT0), norm_rel(gCi, rCi)
     print("fp32 adjoint norm-relative errors: gT0 %.3e gCi %.3e" % (e0, e1), flush=True)
     assert e0 <= 1e-5 and e1 <= 1e-4
+    eT0, eCi = _emulated32(T0, Ci, r, s, nt)
+    np.testing.assert_array_equal(gT0, eT0)
+    np.testing.assert_array_equal(gCi, eCi)
 
 
 def test_grad256_dot_product(lib):

@@ -1,5 +1,6 @@
 """The large gradient form: 1024^3 FP32 (4.3 GB per field), a checkpoint
-every 32 steps (workspace of 47 fields, about 202 GB), 64-bit offsets."""
+every 32 steps (at nt = 500 a workspace of 26 fields, about 112 GB; here
+nt = 40), 64-bit offsets."""
 import numpy as np
 import pytest
 

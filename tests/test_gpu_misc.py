@@ -48,8 +48,7 @@ def test_unaligned_fields(lib):
         T, T2, C = (b[off:off + n].view(shape) for b in bufs)
         T.copy_(to_dev(T0, torch.bfloat16))
         C.copy_(to_dev(Ci, torch.bfloat16))
-        lib.set_sr_seed(3, 0)
-        lib.run(T, T2, C, *sc, 5)       # odd: ends with a copy T2 -> T
+        lib.run(T, T2, C, *sc, 5, cfg=lib.Config(sr_seed=3))       # odd: ends with a copy T2 -> T
         torch.cuda.synchronize()
         outs.append(T.clone())
     assert torch.equal(outs[0], outs[1])
@@ -65,13 +64,11 @@ def test_extreme_shapes(lib, shape):
     s = oracle.scalars(nx, ny, nz, Ci)
     sc = (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
     ref = oracle.forward(T0, Ci, *sc, 7)
-    for kernel in (lib.KERNEL_NAIVE, lib.KERNEL_ZMARCH, lib.KERNEL_TB2):
-        lib.set_kernel(kernel)
+    for kernel in (lib.KERNEL_NAIVE, lib.KERNEL_ZMARCH, lib.KERNEL_TB2, lib.KERNEL_AUTO):
         T = to_dev(T0, torch.float64)
-        lib.run(T, torch.empty_like(T), to_dev(Ci, torch.float64), *sc, 7)
+        lib.run(T, torch.empty_like(T), to_dev(Ci, torch.float64), *sc, 7, cfg=lib.Config(kernel=kernel))
         torch.cuda.synchronize()
         np.testing.assert_array_equal(to_host(T), ref)
-    lib.set_kernel(lib.KERNEL_AUTO)
     g = rng.standard_normal(shape)
     rT0, rCi = oracle.reverse(T0, Ci, g, *sc, 7)
     T0d, Cid = to_dev(T0, torch.float64), to_dev(Ci, torch.float64)
@@ -96,6 +93,25 @@ def test_python_binding_rejects(lib):
     ws = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(ValueError):
         lib.run(T, torch.empty_like(T), T.clone(), 1.0, 1e-3, 1.0, 1.0, 1.0, 10, ckpt=ws, ckpt_every=3)
+    # host buffers never reach the library (a GPU kernel would fault on them)
+    g, gT0, gCi = torch.zeros_like(T), torch.empty_like(T), torch.empty_like(T)
+    wsz = lib.adjoint_workspace_bytes(T.shape, 10, 3, torch.float64)
+    for bad_ws in (torch.empty(wsz, dtype=torch.uint8), torch.empty(2 * wsz, dtype=torch.uint8, device="cuda")[::2]):
+        with pytest.raises(ValueError):
+            lib.adjoint_run(T, T, g, gT0, gCi, bad_ws, False, 1.0, 1e-3, 1.0, 1.0, 1.0, 10, 3)
+    with pytest.raises(ValueError):
+        lib.run(T, torch.empty_like(T), T.clone(), 1.0, 1e-3, 1.0, 1.0, 1.0, 10,
+                ckpt=torch.empty(wsz, dtype=torch.uint8), ckpt_every=3)
+    src = torch.ones(64, dtype=torch.uint8, device="cuda")
+    for dst in (torch.empty(64, dtype=torch.uint8), torch.empty(128, dtype=torch.uint8, device="cuda")[::2]):
+        with pytest.raises(ValueError):
+            lib.copy_(dst, src)
+    with pytest.raises(ValueError):
+        lib.copy_(torch.empty(64, dtype=torch.uint8, device="cuda"), torch.ones(64, dtype=torch.uint8))
+    # a configuration the library does not instantiate is refused before any launch
+    with pytest.raises(lib.Diff3dError):
+        lib.run(T, torch.empty_like(T), T.clone(), 1.0, 1e-3, 1.0, 1.0, 1.0, 10,
+                cfg=lib.Config(zmarch=lib.Tile(p=(3, 3, 3, 3))))
 
 
 def test_side_stream(lib):
