@@ -252,6 +252,21 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
 int diff3d_loss(const void* T, const void* Tt, void* seed, size_t n, int dtype, double* acc,
                 void* stream);
 
+/* diff3d_loss for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result bits, with the partial sums in a
+ * fixed array of DIFF3D_NOALLOC_PARTIALS doubles that the library holds on
+ * each GPU it runs on until the process ends, instead of caller scratch.
+ * out is one device double that receives L; seed as in diff3d_loss.  Every
+ * call on one GPU uses that GPU's array, so calls that overlap on one GPU
+ * (concurrent streams or threads) race and must be serialised by the
+ * caller.  Allocates nothing, enqueues no memset.  EINVAL for NULL pointers
+ * or n outside 1 .. 2^40-1; EHIP if the array's device address cannot be
+ * looked up (first call on a device). */
+#define DIFF3D_NOALLOC_PARTIALS 1024
+int diff3d_loss_noalloc(const void* T, const void* Tt, void* seed, size_t n, int dtype, double* out,
+                        void* stream);
+
 /* Squared 2-norm of n elements of x, accumulated in FP64 into acc[0]
  * (deterministic order). */
 int diff3d_norm2(const void* x, size_t n, int dtype, double* acc, void* stream);

@@ -70,6 +70,7 @@ _SIGS = {
     "diff3d_adjoint_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _sz, _i, _i, _i, _i, _d, _d, _d, _d, _d, _i, _i, _i,
                             _vp, _cfgp], _i),
     "diff3d_loss": ([_vp, _vp, _vp, _sz, _i, _vp, _vp], _i),
+    "diff3d_loss_noalloc": ([_vp, _vp, _vp, _sz, _i, _vp, _vp], _i),
     "diff3d_norm2": ([_vp, _sz, _i, _vp, _vp], _i),
     "diff3d_copy": ([_vp, _vp, _sz, _vp], _i),
     "diff3d_philox4x32_10": ([_u32p, _u32p, _u32p], None),
@@ -377,6 +378,22 @@ def loss(T: torch.Tensor, Tt: torch.Tensor, seed: torch.Tensor | None = None) ->
     with _on(T):
         _check(_lib.diff3d_loss(_p(T), _p(Tt), _p(seed), T.numel(), _code(T), _p(acc), _stream(T)), "loss")
     return acc[0]
+
+
+def loss_into(out: torch.Tensor, T: torch.Tensor, Tt: torch.Tensor, seed: torch.Tensor | None = None) -> None:
+    """The loss of loss() written into ``out`` (a float64 device tensor of at
+    least one element), without caller scratch: the library's fixed per-GPU
+    array holds the partial sums, so calls that overlap on one GPU race."""
+    _field(T, "T")
+    _field(Tt, "Tt", T)
+    if seed is not None:
+        _field(seed, "seed", T)
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float64 or out.numel() < 1 or \
+            not out.is_contiguous() or out.device != T.device:
+        raise ValueError("out must be a contiguous float64 tensor on T's device")
+    with _on(T):
+        _check(_lib.diff3d_loss_noalloc(_p(T), _p(Tt), _p(seed), T.numel(), _code(T), _p(out), _stream(T)),
+               "loss_noalloc")
 
 
 def norm2(x: torch.Tensor) -> torch.Tensor:

@@ -8,6 +8,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "adjoint_launch.hpp"
 #include "diff2d_launch.hpp"
 #include "diff3d.h"
@@ -54,6 +57,37 @@ int run_loop(int dtype, void* T, void* T2, const void* Ci, int nx, int ny, int n
 
 inline int nck_of(int nt, int C) { return nt > 0 ? (nt + C - 1) / C : 0; }
 
+// Device scratch of diff3d_loss_noalloc: the partial sums of its first
+// reduction pass (one per workgroup, at most kRedParts).  Every GPU the
+// library runs on holds its own copy until the process ends; calls on one
+// GPU share it.
+__device__ __align__(256) double scratch[kRedParts];
+
+// The device address of `scratch` on each device, looked up once per device
+// with that device current (the host-side name is only a stand-in).
+constexpr int kMaxDevices = 64;
+std::atomic<double*> g_scratch_addr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+int scratch_on_current_device(double** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return DIFF3D_EHIP;
+    double* p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_addr[dev].load(std::memory_order_acquire);
+        if (!p) {
+            void* q = nullptr;
+            if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return DIFF3D_EHIP;
+            p = static_cast<double*>(q);
+            g_scratch_addr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return DIFF3D_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -97,21 +131,31 @@ int diff3d_max(const void* x, size_t n, int dtype, double* acc, void* stream)
 {
     if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
     if (!x || !acc || n == 0) return DIFF3D_EINVAL;
-    return reduce_dispatch<RED_MAX>(dtype, x, nullptr, nullptr, n, acc, as_stream(stream));
+    return reduce_dispatch<RED_MAX>(dtype, x, nullptr, nullptr, n, acc + 1, acc, as_stream(stream));
 }
 
 int diff3d_loss(const void* T, const void* Tt, void* seed, size_t n, int dtype, double* acc, void* stream)
 {
     if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
     if (!T || !Tt || !acc || n == 0) return DIFF3D_EINVAL;
-    return reduce_dispatch<RED_SUMSQ_DIFF>(dtype, T, Tt, seed, n, acc, as_stream(stream));
+    return reduce_dispatch<RED_SUMSQ_DIFF>(dtype, T, Tt, seed, n, acc + 1, acc, as_stream(stream));
+}
+
+int diff3d_loss_noalloc(const void* T, const void* Tt, void* seed, size_t n, int dtype, double* out, void* stream)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (!T || !Tt || !out || n == 0 || n >= kMaxPoints) return DIFF3D_EINVAL;
+    double* partials = nullptr;
+    const int rc = scratch_on_current_device(&partials);
+    if (rc) return rc;
+    return reduce_dispatch<RED_SUMSQ_DIFF>(dtype, T, Tt, seed, n, partials, out, as_stream(stream));
 }
 
 int diff3d_norm2(const void* x, size_t n, int dtype, double* acc, void* stream)
 {
     if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
     if (!x || !acc || n == 0) return DIFF3D_EINVAL;
-    return reduce_dispatch<RED_SUMSQ>(dtype, x, nullptr, nullptr, n, acc, as_stream(stream));
+    return reduce_dispatch<RED_SUMSQ>(dtype, x, nullptr, nullptr, n, acc + 1, acc, as_stream(stream));
 }
 
 int diff3d_copy(void* dst, const void* src, size_t bytes, void* stream)

@@ -77,9 +77,11 @@ __global__ void copy_tail(unsigned char* __restrict__ dst, const unsigned char* 
 }
 
 // ------------------------------------------------------------------ reductions
-// Pass 1: block b reduces a fixed grid-stride subset into acc[1 + b]
-// (fixed tree in LDS); pass 2: one block reduces acc[1 .. nparts] into
-// acc[0].  Same grid and same order on every call: deterministic.
+// Pass 1: block b reduces a fixed grid-stride subset into partials[b]
+// (fixed tree in LDS); pass 2: one block reduces partials[0 .. nparts-1]
+// into out[0].  Same grid and same order on every call: deterministic.
+// Every partial the second pass reads is written by the first, so the
+// partials need no clearing.
 enum { RED_MAX = 0, RED_SUMSQ_DIFF = 1, RED_SUMSQ = 2 };
 constexpr int kRedParts = 1024;
 
@@ -87,7 +89,7 @@ template <int DT, int OP>
 __global__ __launch_bounds__(256) void reduce_partial(const typename Traits<DT>::S* __restrict__ x,
                                                       const typename Traits<DT>::S* __restrict__ y,
                                                       typename Traits<DT>::S* __restrict__ seed, size_t n,
-                                                      double* __restrict__ acc)
+                                                      double* __restrict__ partials)
 {
     using Tr = Traits<DT>;
     __shared__ double sh[256];
@@ -119,15 +121,16 @@ __global__ __launch_bounds__(256) void reduce_partial(const typename Traits<DT>:
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) acc[1 + blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
 }
 
 template <int OP>
-__global__ __launch_bounds__(1024) void reduce_final(double* __restrict__ acc, int nparts)
+__global__ __launch_bounds__(1024) void reduce_final(const double* __restrict__ partials, int nparts,
+                                                     double* __restrict__ out)
 {
     __shared__ double sh[1024];
     const double id = OP == RED_MAX ? -__builtin_huge_val() : 0.0;
-    sh[threadIdx.x] = (int)threadIdx.x < nparts ? acc[1 + threadIdx.x] : id;
+    sh[threadIdx.x] = (int)threadIdx.x < nparts ? partials[threadIdx.x] : id;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(1024) void reduce_final(double* __restrict__ acc, i
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) acc[0] = OP == RED_SUMSQ_DIFF ? 0.5 * sh[0] : sh[0];
+    if (threadIdx.x == 0) out[0] = OP == RED_SUMSQ_DIFF ? 0.5 * sh[0] : sh[0];
 }
 
 }  // namespace diff3d

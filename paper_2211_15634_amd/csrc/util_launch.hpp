@@ -69,27 +69,29 @@ int boundary_dispatch(int dtype, void* dst, const void* src, int nx, int ny, int
 
 
 // ------------------------------------------------------------------ reductions
+// partials: at least kRedParts doubles of device scratch; out: one double.
 template <int DT, int OP>
-int reduce_launch(const void* x, const void* y, void* seed, size_t n, double* acc, hipStream_t st)
+int reduce_launch(const void* x, const void* y, void* seed, size_t n, double* partials, double* out, hipStream_t st)
 {
     using S = typename Traits<DT>::S;
     size_t parts = (n + 255) / 256;
     if (parts > (size_t)kRedParts) parts = kRedParts;
     if (parts < 1) parts = 1;
     reduce_partial<DT, OP><<<(unsigned)parts, 256, 0, st>>>(static_cast<const S*>(x), static_cast<const S*>(y),
-                                                            static_cast<S*>(seed), n, acc);
-    reduce_final<OP><<<1, 1024, 0, st>>>(acc, (int)parts);
+                                                            static_cast<S*>(seed), n, partials);
+    reduce_final<OP><<<1, 1024, 0, st>>>(partials, (int)parts, out);
     return hip_status();
 }
 
 template <int OP>
-int reduce_dispatch(int dtype, const void* x, const void* y, void* seed, size_t n, double* acc, hipStream_t st)
+int reduce_dispatch(int dtype, const void* x, const void* y, void* seed, size_t n, double* partials, double* out,
+                    hipStream_t st)
 {
     switch (dtype) {
-    case DIFF3D_F64: return reduce_launch<DIFF3D_F64, OP>(x, y, seed, n, acc, st);
-    case DIFF3D_F32: return reduce_launch<DIFF3D_F32, OP>(x, y, seed, n, acc, st);
+    case DIFF3D_F64: return reduce_launch<DIFF3D_F64, OP>(x, y, seed, n, partials, out, st);
+    case DIFF3D_F32: return reduce_launch<DIFF3D_F32, OP>(x, y, seed, n, partials, out, st);
     case DIFF3D_BF16:
-    case DIFF3D_BF16_RNE: return reduce_launch<DIFF3D_BF16_RNE, OP>(x, y, seed, n, acc, st);
+    case DIFF3D_BF16_RNE: return reduce_launch<DIFF3D_BF16_RNE, OP>(x, y, seed, n, partials, out, st);
     default: return DIFF3D_EDTYPE;
     }
 }
