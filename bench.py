@@ -22,7 +22,6 @@ Profiling helpers (rocprofv3 runs them; see the files under profiles/):
 from __future__ import annotations
 
 import argparse
-import csv
 import glob
 import hashlib
 import json
@@ -70,44 +69,41 @@ def log(*a):
 
 
 # ------------------------------------------------------------------ profiles
-def _rows(pattern):
+# rocprofv3 writes its results as an SQLite database (<dir>/<name>_results.db);
+# these helpers read the per-dispatch counters and the kernel statistics
+# from it and write the short summaries kept under profiles/.
+def _db_rows(d, query):
+    import sqlite3
     out = []
-    for path in sorted(glob.glob(pattern, recursive=True)):
-        with open(path, newline="") as f:
-            out += list(csv.DictReader(f))
+    for path in sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True)):
+        con = sqlite3.connect(path)
+        try:
+            out += list(con.execute(query))
+        finally:
+            con.close()
     return out
 
 
-def _col(row, *names):
-    low = {k.lower(): v for k, v in row.items()}
-    for n in names:
-        if n.lower() in low:
-            return low[n.lower()]
-    raise KeyError(names)
+def _counters(d):
+    """{counter: [(dispatch id, kernel name, value), ...]} in dispatch order."""
+    out = {}
+    for disp, name, counter, value in _db_rows(
+            d, "select dispatch_id, kernel_name, counter_name, value from counters_collection order by dispatch_id"):
+        out.setdefault(counter, []).append((disp, name, float(value)))
+    return out
 
 
 def summarize_traffic(fetch_dir, write_dir, kernel, steps, workload, nbytes_alg, out_prefix, command):
     """FETCH_SIZE / WRITE_SIZE per dispatch (KiB) from two rocprofv3 --pmc runs
     of --traffic-probe, scaled by what each counter reads for the 1 GiB copy
     launched first; writes <out_prefix>.json and .md."""
-    def per_dispatch(d, counter):
-        vals = {}
-        for r in _rows(os.path.join(d, "**", "*counter_collection.csv")):
-            if _col(r, "Counter_Name") != counter:
-                continue
-            key = int(_col(r, "Dispatch_Id"))
-            name = _col(r, "Kernel_Name")
-            vals.setdefault(key, [name, 0.0])
-            vals[key][1] += float(_col(r, "Counter_Value"))
-        return [vals[k] for k in sorted(vals)]
-
-    fetch = per_dispatch(fetch_dir, "FETCH_SIZE")
-    write = per_dispatch(write_dir, "WRITE_SIZE")
-    cf = [v for n, v in fetch if "copy16" in n]
-    cw = [v for n, v in write if "copy16" in n]
-    kf = [v for n, v in fetch if kernel in n]
-    kw = [v for n, v in write if kernel in n]
-    kname = next(n for n, _ in fetch if kernel in n)
+    fetch = _counters(fetch_dir)["FETCH_SIZE"]
+    write = _counters(write_dir)["WRITE_SIZE"]
+    cf = [v for _, n, v in fetch if "copy16" in n]
+    cw = [v for _, n, v in write if "copy16" in n]
+    kf = [v for _, n, v in fetch if kernel in n]
+    kw = [v for _, n, v in write if kernel in n]
+    kname = next(n for _, n, _ in fetch if kernel in n).split("(")[0]
     gib_kib = 1024.0 * 1024.0
     fs = statistics.median(cf) / gib_kib
     ws = statistics.median(cw) / gib_kib
@@ -126,10 +122,10 @@ def summarize_traffic(fetch_dir, write_dir, kernel, steps, workload, nbytes_alg,
              "One launch advances %d time step(s).  Compulsory bytes per launch (read T and Ci, write T2 once): "
              "%d B." % (steps, nbytes_alg), "", "Commands (repository root, one MI355X):", "", "```", command, "```",
              "", "| dispatch | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |", "|---|---|---|"]
-    for i, (a, b) in enumerate(zip(cf, cw)):
-        lines.append("| copy16, 1 GiB, #%d | %.1f | %.1f |" % (i + 1, a, b))
-    for i, (a, b) in enumerate(zip(kf, kw)):
-        lines.append("| kernel #%d | %.1f | %.1f |" % (i + 1, a, b))
+    for i, (x, y) in enumerate(zip(cf, cw)):
+        lines.append("| copy16, 1 GiB, #%d | %.1f | %.1f |" % (i + 1, x, y))
+    for i, (x, y) in enumerate(zip(kf, kw)):
+        lines.append("| kernel #%d | %.1f | %.1f |" % (i + 1, x, y))
     lines += ["", "Calibration with the copy of known size (1 GiB read and written): FETCH_SIZE reports %.5f of "
               "the bytes read, WRITE_SIZE %.5f of the bytes written.  Scaled, per launch (median):" % (fs, ws), "",
               "- fetched %.4f GB, written %.4f GB, total %.4f GB (%.3f x the compulsory bytes)" %
@@ -141,18 +137,39 @@ def summarize_traffic(fetch_dir, write_dir, kernel, steps, workload, nbytes_alg,
 
 
 def summarize_trace(trace_dir, out_md, command, top=14):
-    rows = _rows(os.path.join(trace_dir, "**", "*kernel_stats.csv"))
+    rows = _db_rows(trace_dir, "select name, total_calls, total_duration, average, percentage from top_kernels")
     lines = ["# rocprofv3 kernel trace summary", "", "Command (repository root, one MI355X):", "", "```", command,
              "```", "", "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
-    rows.sort(key=lambda r: -float(_col(r, "TotalDurationNs")))
-    for r in rows[:top]:
-        name = _col(r, "Name")
-        lines.append("| `%s` | %s | %.1f | %.2f | %.2f |" % (name[:120], _col(r, "Calls"),
-                                                            float(_col(r, "TotalDurationNs")) / 1e3,
-                                                            float(_col(r, "AverageNs")) / 1e3,
-                                                            float(_col(r, "Percentage"))))
+    rows.sort(key=lambda r: -float(r[2]))
+    for name, calls, total, avg, pct in rows[:top]:
+        lines.append("| `%s` | %s | %.1f | %.2f | %.2f |" % (name.split("(")[0][:120], calls, float(total),
+                                                            float(avg), float(pct)))
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_sq(dir1, dir2, kernel, title, out_md, command):
+    """Shader-sequencer counters of the third dispatch of `kernel` from two
+    rocprofv3 --pmc runs, with the derived issue and wait fractions."""
+    vals = {}
+    for d in (dir1, dir2):
+        for counter, rows in _counters(d).items():
+            ks = [v for _, n, v in rows if kernel in n]
+            if ks:
+                vals[counter] = ks[min(2, len(ks) - 1)]
+    g = lambda c: vals.get(c, float("nan"))
+    lines = ["# Shader-sequencer counters, %s" % title, "", "Commands (repository root, one MI355X):", "", "```",
+             command, "```", "", "| counter | value |", "|---|---|"]
+    for c in sorted(vals):
+        lines.append("| %s | %.4g |" % (c, vals[c]))
+    lines += ["| SQ_WAIT_ANY / SQ_WAVE_CYCLES | %.3f |" % (g("SQ_WAIT_ANY") / g("SQ_WAVE_CYCLES")),
+              "| SQ_ACTIVE_INST_ANY / SQ_WAVE_CYCLES | %.3f |" % (g("SQ_ACTIVE_INST_ANY") / g("SQ_WAVE_CYCLES")),
+              "| SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES | %.3f |" % (g("SQ_ACTIVE_INST_VALU") / g("SQ_WAVE_CYCLES")),
+              "| SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES | %.3f |" % (g("SQ_WAIT_INST_LDS") / g("SQ_WAVE_CYCLES")),
+              "| SQ_INSTS_SALU / SQ_INSTS_VALU | %.3f |" % (g("SQ_INSTS_SALU") / g("SQ_INSTS_VALU")), ""]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
     print("\n".join(lines))
 
 
@@ -229,6 +246,8 @@ def main():
                          "(for counter runs)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR")
+    ap.add_argument("--summarize-sq", nargs=2, metavar=("SQ1_DIR", "SQ2_DIR"))
+    ap.add_argument("--title", default="")
     ap.add_argument("--kernel", default="step_tbs<0, 4")
     ap.add_argument("--workload", default="bump512_f64")
     ap.add_argument("--steps-per-launch", type=int, default=4)
@@ -243,6 +262,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.out, args.command)
+        return
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq[0], args.summarize_sq[1], args.kernel, args.title, args.out, args.command)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

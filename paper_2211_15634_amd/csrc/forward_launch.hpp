@@ -233,7 +233,7 @@ template <> struct TbsDefaults<DIFF3D_F32> {
     static constexpr SKey key[5] = {{0}, {0}, {2, 64, 64, 1024, 0}, {3, 128, 32, 1024, 0}, {4, 64, 48, 768, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_BF16> {
-    static constexpr int S = 3;
+    static constexpr int S = 4;
     static constexpr SKey key[5] = {{0}, {0}, {2, 64, 32, 1024, 0}, {3, 64, 32, 1024, 0}, {4, 64, 32, 1024, 0}};
 };
 template <> struct TbsDefaults<DIFF3D_BF16_RNE> {

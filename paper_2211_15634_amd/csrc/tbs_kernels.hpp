@@ -28,14 +28,34 @@ namespace diff3d {
 // the output level is rounded to the storage type, so FP64 and FP32 results
 // are bit-identical to S single steps and BF16 rounds once per pass.
 //
-// BF16 with round-to-nearest on 1024 threads and S >= 3 asks for eight waves
-// per SIMD (at most 64 VGPRs, two workgroups per CU; its LDS allows it): it
-// fits without spills, and four-step passes at 512^3 take 103 us per step
-// against 147 us at one workgroup per CU (two-step passes: 136 us).
+// BF16 on 1024 threads and S >= 3 asks for eight waves per SIMD (at most 64
+// VGPRs, two workgroups per CU; its LDS allows it): round to nearest fits
+// without spills, and four-step passes at 512^3 take 100 us per step against
+// 147 us at one workgroup per CU (two-step passes: 136 us); stochastic
+// rounding fits with its raw-value rings, 144 us per step (one workgroup
+// per CU: 174 us).
+// The value of the next (UP) or previous lane of the wave (DPP wave shift by
+// one lane; the end lanes get their own value back, unused: the region's
+// outermost columns are never updated).
+template <class T, bool UP>
+__device__ inline T lane_shift(T v)
+{
+    constexpr int ctrl = UP ? 0x130 : 0x138;     // wave_shl:1 / wave_shr:1
+    if constexpr (sizeof(T) == 8) {
+        const int2 w = __builtin_bit_cast(int2, v);
+        const int lo = __builtin_amdgcn_update_dpp(w.x, w.x, ctrl, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(w.y, w.y, ctrl, 0xF, 0xF, false);
+        return __builtin_bit_cast(T, int2{lo, hi});
+    } else {
+        const int w = __builtin_bit_cast(int, v);
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(w, w, ctrl, 0xF, 0xF, false));
+    }
+}
+
 template <int DT, int S, int W0, int H0, int NTH>
 constexpr int tbs_min_waves()
 {
-    return (DT == DIFF3D_BF16_RNE && NTH == 1024 && S >= 3) ? 8 : 1;
+    return ((DT == DIFF3D_BF16_RNE || DT == DIFF3D_BF16) && NTH == 1024 && S >= 3) ? 8 : 1;
 }
 
 template <int DT, int S, int W0, int H0, int NTH, bool NT>
@@ -58,7 +78,7 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     constexpr int NB = 9;
     constexpr bool SR_BATCH = Tr::sr && NB * K <= 64;
     constexpr int NWAVE = NTH / 64;
-    __shared__ uint32_t srw[SR_BATCH ? NWAVE : 1][SR_BATCH ? 64 : 1][4];
+    __shared__ uint32_t srw[SR_BATCH ? NWAVE : 1][SR_BATCH ? NB * K : 1][4];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
@@ -111,6 +131,9 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     // two workgroups per CU (8%); FP64 evaluates them per use (3% faster
     // there, for no reason visible in the code).
     constexpr bool kMaskTable = DT == DIFF3D_F32 || DT == DIFF3D_BF16 || DT == DIFF3D_BF16_RNE;
+    // x neighbours by cross-lane moves: FP64 and FP32 with W0 = 64 (1.5%
+    // faster at 512^3; the BF16 kernels, at 64 VGPRs, are slower with them)
+    constexpr bool kLaneX = W0 == 64 && (DT == DIFF3D_F64 || DT == DIFF3D_F32);
     bool act[S + 1][K];
 #pragma unroll
     for (int s = 1; s <= S; ++s)
@@ -160,18 +183,47 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     // at planes p, p-1, .., p-S+1 (ci[j] holds plane p+1-j); and two slots
     // each for the loads in flight (T planes p+2 and p+3, Ci planes p+1 and
     // p+2): a load is issued two plane iterations before its use.
+    // With stochastically rounded BF16 the loads in flight and the Ci ring
+    // hold raw stored values, two slots per 32-bit register, widened (and
+    // multiplied by lam) where they are used: the kernel then fits 64 VGPRs
+    // (two workgroups per CU) with its random-word exchange.  (Round to
+    // nearest fits without, and is 3% slower with it.)
+    constexpr bool PK = Tr::sr && K % 2 == 0;
+    constexpr int KP = PK ? K / 2 : 1;
     C t0[3][K];
     C u[S > 1 ? S - 1 : 1][2][K];
-    C ci[S + 1][K];
-    C lt[2][K], lc[2][K];
+    C ci[PK ? 1 : S + 1][PK ? 1 : K];
+    C lt[PK ? 1 : 2][PK ? 1 : K], lc[PK ? 1 : 2][PK ? 1 : K];
+    uint32_t cip[PK ? S + 1 : 1][KP], ltp[PK ? 2 : 1][KP], lcp[PK ? 2 : 1][KP];
+    auto widen = [&](uint32_t w, int k) __attribute__((always_inline)) -> C {
+        return __uint_as_float((k & 1) ? (w & 0xFFFF0000u) : (w << 16));
+    };
+    auto load_pairs = [&](const S_* f, const size_t* bs, int z, uint32_t (&dst)[KP]) __attribute__((always_inline)) {
+        const size_t zo = sz * (size_t)min(max(z, 0), nz - 1);
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+            const uint32_t lo = (uint32_t)(uint16_t)f[bs[2 * j] + zo];
+            const uint32_t hi = (uint32_t)(uint16_t)f[bs[2 * j + 1] + zo];
+            dst[j] = lo | (hi << 16);
+        }
+    };
+    // lam*Ci of slot k at the plane of level s
+    auto lamci = [&](int s, int k) __attribute__((always_inline)) -> C {
+        if constexpr (PK)
+            return a.lam * widen(cip[s][k / 2], k);
+        else
+            return ci[s][k];
+    };
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
         for (int s = 0; s < (S > 1 ? S - 1 : 1); ++s)
 #pragma unroll
             for (int i = 0; i < 2; ++i) u[s][i][k] = C(0);
+        if constexpr (!PK) {
 #pragma unroll
-        for (int j = 0; j <= S; ++j) ci[j][k] = C(0);
+            for (int j = 0; j <= S; ++j) ci[j][k] = C(0);
+        }
     }
 
     const int p0 = zb - S + 1;              // first plane of level 1
@@ -179,26 +231,40 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     load_T(p0 - 1, t0[0]);
     load_T(p0, t0[1]);
     load_T(p0 + 1, t0[2]);
-    load_T(p0 + 2, lt[0]);
-    load_Ci(p0, ci[1]);
-    lam_ci(ci[1]);
-    load_Ci(p0 + 1, lc[0]);
+    if constexpr (PK) {
+#pragma unroll
+        for (int j = 0; j <= S; ++j)
+#pragma unroll
+            for (int q = 0; q < KP; ++q) cip[j][q] = 0u;
+        load_pairs(a.T, base, p0 + 2, ltp[0]);
+        load_pairs(a.Ci, cbase, p0, cip[1]);
+        load_pairs(a.Ci, cbase, p0 + 1, lcp[0]);
+    } else {
+        load_T(p0 + 2, lt[0]);
+        load_Ci(p0, ci[1]);
+        lam_ci(ci[1]);
+        load_Ci(p0 + 1, lc[0]);
+    }
     stage(0, 1, t0[1]);                     // plane p0 is read as "the previous iteration's" buffer
 
-    // random words of this iteration's stored points (slot k)
-    uint32_t rnd[SR_BATCH ? K : 1];
+    // Stochastic rounding words.  A wave's 64 points of slot k are
+    // consecutive in memory, from index i0 (lane 0's); lane l's point is
+    // i0 + l, in block (i0 % 8 + l) / 8 after lane 0's, at position
+    // (i0 % 8 + l) % 8.  Only i0 % 8 (wave-uniform) is kept per slot.
+    int i0mod[SR_BATCH ? K : 1];
     auto draw = [&](int p) __attribute__((always_inline)) {
         if constexpr (SR_BATCH) {
             const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
             const int z = p - S + 1;             // the plane level S reaches in this iteration
-            // first block of each slot: from lane 0's point (wave-uniform)
             size_t g0[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const size_t g = gidx(k, z) >> 3;
-                const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)g);
-                const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(g >> 32));
-                g0[k] = ((size_t)hi << 32) | lo;
+                const size_t i0 = gidx(k, z) - (size_t)lane;
+                const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)i0);
+                const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(i0 >> 32));
+                const size_t u = ((size_t)hi << 32) | lo;
+                g0[k] = u >> 3;
+                i0mod[k] = (int)(lo & 7u);
             }
             // lane L computes block b of slot k, L = k*NB + b
             if (lane < NB * K) {
@@ -214,22 +280,18 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
                 srw[wv][lane][3] = r.w;
             }
             __builtin_amdgcn_wave_barrier();   // the wave's LDS writes precede its reads (in order per wave)
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const size_t i = gidx(k, z);
-                const int b = min(max((int)((i >> 3) - g0[k]), 0), NB - 1);
-                const unsigned j = (unsigned)(i & 7);
-                const uint32_t w = srw[wv][k * NB + b][j >> 1];
-                rnd[k] = (j & 1) ? (w & 0xFFFF0000u) : (w << 16);
-            }
-            __builtin_amdgcn_wave_barrier();
         }
     };
     auto rounding_at = [&](int k, int z) __attribute__((always_inline)) -> uint32_t {
-        if constexpr (SR_BATCH)
-            return rnd[k];
-        else
+        if constexpr (SR_BATCH) {
+            const int wv = (int)(threadIdx.x >> 6);
+            const int off = i0mod[k] + (int)(threadIdx.x & 63);
+            const int j = off & 7;
+            const uint32_t w = srw[wv][k * NB + (off >> 3)][j >> 1];
+            return (j & 1) ? (w & 0xFFFF0000u) : (w << 16);
+        } else {
             return rounding(gidx(k, z));
+        }
     };
 
     // One plane iteration; PAR = (p - p0) & 1 selects the load slots.
@@ -238,8 +300,13 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
         constexpr int buf = PAR, rbuf = PAR ^ 1;
         draw(p);
         // 1. loads two planes ahead
-        load_T(p + 3, lt[PAR ^ 1]);
-        load_Ci(p + 2, lc[PAR ^ 1]);
+        if constexpr (PK) {
+            load_pairs(a.T, base, p + 3, ltp[PAR ^ 1]);
+            load_pairs(a.Ci, cbase, p + 2, lcp[PAR ^ 1]);
+        } else {
+            load_T(p + 3, lt[PAR ^ 1]);
+            load_Ci(p + 2, lc[PAR ^ 1]);
+        }
         lds_barrier();
         // 2. level 0, plane p+1, for level 1 of the next iteration
         stage(0, buf, t0[2]);
@@ -259,12 +326,20 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
                 const C ce = s == 1 ? t0[1][k] : u[s - 2][1][k];
                 const C zp = prev[k];
                 C v = ce;
+                // FP64/FP32 with whole region rows per wave: the x neighbours
+                // are the adjacent lanes' centre values (cross-lane moves,
+                // outside the branch so every lane takes part)
+                C xmd = ce, xpd = ce;
+                if constexpr (kLaneX) {
+                    xmd = lane_shift<C, false>(ce);
+                    xpd = lane_shift<C, true>(ce);
+                }
                 if (zact && (kMaskTable ? act[s][k] : in_level(k, s) && interior_xy(k))) {
-                    const C xm = lds[s - 1][rbuf][rr[k]][cc[k] - 1];
-                    const C xp = lds[s - 1][rbuf][rr[k]][cc[k] + 1];
+                    const C xm = kLaneX ? xmd : lds[s - 1][rbuf][rr[k]][cc[k] - 1];
+                    const C xp = kLaneX ? xpd : lds[s - 1][rbuf][rr[k]][cc[k] + 1];
                     const C ym = lds[s - 1][rbuf][rr[k] - 1][cc[k]];
                     const C yp = lds[s - 1][rbuf][rr[k] + 1][cc[k]];
-                    const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, ci[s][k], a);
+                    const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, lamci(s, k), a);
                     if (s < S) {
                         v = w;
                     } else if (z >= zb && z < ze &&
@@ -293,15 +368,28 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
                 for (int k = 0; k < K; ++k) prev[k] = out[k];
             }
         }
+        if constexpr (SR_BATCH) __builtin_amdgcn_wave_barrier();   // reads done before the next draw writes
         // 4. shift level 0 and Ci; the older slot (plane p+2, Ci plane p+1) enters
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             t0[0][k] = t0[1][k];
             t0[1][k] = t0[2][k];
-            t0[2][k] = lt[PAR][k];
+            if constexpr (PK) {
+                t0[2][k] = widen(ltp[PAR][k / 2], k);
+            } else {
+                t0[2][k] = lt[PAR][k];
 #pragma unroll
-            for (int j = S; j >= 2; --j) ci[j][k] = ci[j - 1][k];
-            ci[1][k] = a.lam * lc[PAR][k];
+                for (int j = S; j >= 2; --j) ci[j][k] = ci[j - 1][k];
+                ci[1][k] = a.lam * lc[PAR][k];
+            }
+        }
+        if constexpr (PK) {
+#pragma unroll
+            for (int q = 0; q < KP; ++q) {
+#pragma unroll
+                for (int j = S; j >= 2; --j) cip[j][q] = cip[j - 1][q];
+                cip[1][q] = lcp[PAR][q];
+            }
         }
     };
     for (int p = p0; p <= plast; p += 2) {
