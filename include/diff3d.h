@@ -59,11 +59,10 @@ typedef enum {
 
 typedef enum {
     DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps; in
-                                  diff3d_run S-step passes for FP64 (S = 4), FP32 (S = 4;
-                                  3 on x-y planes above 768^2 points), BF16 with
-                                  stochastic rounding (S = 3) and BF16 with
-                                  round-to-nearest (S = 4); in diff3d_adjoint_run
-                                  fused three-step reverse passes */
+                                  diff3d_run S-step passes (S = 4 for FP64 and both BF16
+                                  forms; FP32: S = 4, 3 on x-y planes above 768^2
+                                  points); in diff3d_adjoint_run fused three-step
+                                  reverse passes */
     DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */
     DIFF3D_KERNEL_ZMARCH = 2,  /* x-y tiles marching along z, planes in registers and LDS */
     DIFF3D_KERNEL_TB2 = 3,     /* diff3d_run: two steps per pass (temporal blocking), z-march
@@ -292,6 +291,41 @@ int diff2d_step(void* T2, const void* T, const void* Ci, int nx, int ny, double 
  * nt = 0 leaves T unchanged. */
 int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
                double rdy, int nt, int dtype, void* stream);
+
+/* The finite-difference operators of the paper's kernel notation (Fig. 1
+ * composes the step of @inn, @d2_xi, @d2_yi and @d2_zi), applied to a whole
+ * field.  Every stencil of the library is built of the same device functions,
+ * so these calls show the operation order the steps use.  At interior point
+ * (ix, iy, iz), 1 <= ix <= nx-2 (likewise y, z):
+ *   DIFF3D_OP_INN    A[ix, iy, iz]                        (interior selection)
+ *   DIFF3D_OP_D2_XI  (A[ix+1] - A[ix]) - (A[ix] - A[ix-1]) (along x; likewise
+ *   DIFF3D_OP_D2_YI  along y with stride nx,
+ *   DIFF3D_OP_D2_ZI  along z with stride nx*ny)
+ *   DIFF3D_OP_LAP    (d2x*cx + d2y*cy) + d2z*cz, cx = rdx*rdx (likewise y, z):
+ *                    the weighted Laplacian the step multiplies by lam*Ci*dt
+ * The paper does not print the definition of @d2_xi: the difference of the two
+ * one-sided differences is the reading taken (exactly A[x+1] - 2A[x] + A[x-1]
+ * in real arithmetic).
+ *
+ * `in` is an nx*ny*nz field (layout as above); nz == 1 selects a 2-D field of
+ * nx*ny points (linear index x + nx*y), for which D2_ZI is invalid and LAP
+ * drops the z term (the 2-D step, diff2d_step).  `out` receives the interior,
+ * (nx-2)*(ny-2)*max(nz-2, 1) elements, dense, x fastest, in the arithmetic
+ * type: double for DIFF3D_F64, float for DIFF3D_F32 and both BF16 forms (BF16
+ * inputs are widened exactly; nothing is rounded to BF16).  rdx, rdy, rdz are
+ * used by LAP only (rounded once to float for the FP32 types).  Rejected
+ * (nothing enqueued): unknown op (EINVAL), unknown dtype (EDTYPE), NULL
+ * pointers, nx or ny < 3, nz == 2 or nz < 1, D2_ZI with nz == 1, and `out`
+ * overlapping `in` (EINVAL).  Device pointers, enqueued on `stream`. */
+typedef enum {
+    DIFF3D_OP_INN = 0,
+    DIFF3D_OP_D2_XI = 1,
+    DIFF3D_OP_D2_YI = 2,
+    DIFF3D_OP_D2_ZI = 3,
+    DIFF3D_OP_LAP = 4
+} diff3d_op;
+int diff3d_apply(int op, void* out, const void* in, int nx, int ny, int nz, double rdx, double rdy,
+                 double rdz, int dtype, void* stream);
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the counter-based
  * generator behind the stochastic rounding: out = bijection of ctr under

@@ -76,6 +76,10 @@ def _load():
             lib.emul_forward.restype = i
             lib.emul_reverse32.argtypes = [vp, vp, vp, vp, vp, i, i, i, d, d, d, d, d, i, i, i]
             lib.emul_reverse32.restype = i
+            lib.oracle_apply.argtypes = [i, dp, dp, i, i, i, d, d, d]
+            lib.oracle_apply.restype = i
+            lib.emul_apply32.argtypes = [i, vp, vp, i, i, i, d, d, d, i]
+            lib.emul_apply32.restype = i
             _lib = lib
     return _lib
 
@@ -264,3 +268,47 @@ def emulate_reverse32(T0, Ci, g_nt, lam: float, dt: float, rdx: float, rdy: floa
     if rc != 0:
         raise ValueError("emul_reverse32 failed (%d)" % rc)
     return gT0, gCi
+
+
+# Operators of the kernel notation (Fig. 1): interior selection, second
+# differences along x, y, z, and the weighted Laplacian of the step.
+OP_INN, OP_D2_XI, OP_D2_YI, OP_D2_ZI, OP_LAP = 0, 1, 2, 3, 4
+
+
+def _interior_shape(shape):
+    return tuple(n - 2 for n in shape)
+
+
+def apply(op: int, A, rdx: float = 1.0, rdy: float = 1.0, rdz: float = 1.0) -> np.ndarray:
+    """One operator applied to the FP64 field A, shape (nz, ny, nx) or, for a
+    2-D field, (ny, nx); returns its interior values (each dimension shorter
+    by two)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    if A.ndim == 3:
+        nz, ny, nx = A.shape
+    elif A.ndim == 2:
+        (ny, nx), nz = A.shape, 1
+    else:
+        raise ValueError("apply expects a (nz, ny, nx) or (ny, nx) array")
+    out = np.empty(_interior_shape(A.shape), dtype=np.float64)
+    rc = _load().oracle_apply(int(op), _ptr(out), _ptr(A), nx, ny, nz, rdx, rdy, rdz)
+    if rc != 0:
+        raise ValueError("oracle_apply failed (%d)" % rc)
+    return out
+
+
+def emulate_apply32(op: int, A, storage: int, rdx: float = 1.0, rdy: float = 1.0, rdz: float = 1.0) -> np.ndarray:
+    """One operator in FP32 arithmetic on stored values A (float32, or uint16
+    BF16 bits for the BF16 storage codes), 3-D or 2-D as ``apply``."""
+    A = np.ascontiguousarray(A, dtype=np.float32 if storage == ST_F32 else np.uint16)
+    if A.ndim == 3:
+        nz, ny, nx = A.shape
+    elif A.ndim == 2:
+        (ny, nx), nz = A.shape, 1
+    else:
+        raise ValueError("emulate_apply32 expects a (nz, ny, nx) or (ny, nx) array")
+    out = np.empty(_interior_shape(A.shape), dtype=np.float32)
+    rc = _load().emul_apply32(int(op), _vp(out), _vp(A), nx, ny, nz, rdx, rdy, rdz, int(storage))
+    if rc != 0:
+        raise ValueError("emul_apply32 failed (%d)" % rc)
+    return out

@@ -34,6 +34,12 @@
  * the same expression without the z term,
  *       T2 = T + dt*(lam*Ci*(d2x(T)*(1/dx)^2 + d2y(T)*(1/dy)^2)),
  * on interior points of an nx x ny grid (index ix + nx*iy), boundary fixed.
+ *
+ * The operators of the kernel notation (Fig. 1 writes the step with @inn,
+ * @d2_xi, @d2_yi and @d2_zi), each applied to a whole field: the interior
+ * values, the second difference along one axis at interior points, and the
+ * weighted Laplacian (d2x*(1/dx)^2 + d2y*(1/dy)^2) + d2z*(1/dz)^2, as dense
+ * arrays over the interior.
  */
 #include <math.h>
 #include <stdint.h>
@@ -264,5 +270,44 @@ int oracle_forward2d(double* T, const double* T0, const double* Ci, int nx, int 
     }
     if (a != T) memcpy(T, a, n * sizeof(double));
     free(T2);
+    return 0;
+}
+
+/* ------------------------------------------------------------ operators */
+/* The operators of Fig. 1's kernel notation applied to the field A (nz == 1:
+ * a 2-D field of nx*ny points).  At each interior point, in order x fastest:
+ *   op 0  @inn(A):   A itself;
+ *   op 1  @d2_xi(A): (A[x+1] - A[x]) - (A[x] - A[x-1]), the second difference
+ *                    along x (the paper does not print its definition; this
+ *                    is the difference of the two one-sided differences);
+ *   op 2, op 3: the same along y and along z;
+ *   op 4  (d2x*(rdx*rdx) + d2y*(rdy*rdy)) + d2z*(rdz*rdz), the Laplacian the
+ *         step multiplies by dt*lam*Ci (2-D: d2x*(rdx*rdx) + d2y*(rdy*rdy)).
+ * out holds (nx-2)*(ny-2)*(nz-2) values (2-D: (nx-2)*(ny-2)). */
+int oracle_apply(int op, double* out, const double* A, int nx, int ny, int nz, double rdx, double rdy, double rdz)
+{
+    const int twod = nz == 1;
+    if (op < 0 || op > 4 || nx < 3 || ny < 3 || (!twod && nz < 3) || (twod && op == 3)) return -1;
+    const double cx = rdx * rdx, cy = rdy * rdy, cz = rdz * rdz;
+    const int z0 = twod ? 0 : 1, z1 = twod ? 1 : nz - 1;
+    size_t o = 0;
+    for (int iz = z0; iz < z1; ++iz)
+        for (int iy = 1; iy < ny - 1; ++iy)
+            for (int ix = 1; ix < nx - 1; ++ix) {
+                const double t = A[IDX(ix, iy, iz)];
+                const double d2x = (A[IDX(ix + 1, iy, iz)] - t) - (t - A[IDX(ix - 1, iy, iz)]);
+                const double d2y = (A[IDX(ix, iy + 1, iz)] - t) - (t - A[IDX(ix, iy - 1, iz)]);
+                double d2z = 0.0;
+                if (!twod) d2z = (A[IDX(ix, iy, iz + 1)] - t) - (t - A[IDX(ix, iy, iz - 1)]);
+                double v;
+                switch (op) {
+                case 0: v = t; break;
+                case 1: v = d2x; break;
+                case 2: v = d2y; break;
+                case 3: v = d2z; break;
+                default: v = twod ? d2x * cx + d2y * cy : (d2x * cx + d2y * cy) + d2z * cz; break;
+                }
+                out[o++] = v;
+            }
     return 0;
 }

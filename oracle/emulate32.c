@@ -34,6 +34,9 @@
  *       gCi += ((dt*lam)*lambda)*Lap(T_k)     interior points
  *       mu   = ((dt*lam)*Ci)*lambda            interior points, 0 elsewhere
  *       lambda_k = lambda_{k+1} + Lap(mu)      every point (mu = 0 outside).
+ *   - the operators of the kernel notation (@inn, @d2_xi, @d2_yi, @d2_zi
+ *     and the weighted Laplacian) in FP32 on widened stored values, as the
+ *     FP64 oracle defines them.
  * Built with -ffp-contract=off; x86-64 evaluates float expressions in FP32.
  * Layout: linear index ix + nx*(iy + ny*iz), x fastest.
  */
@@ -346,5 +349,47 @@ int emul_reverse32(const float* T0, const float* Ci, const float* g_nt, float* g
         memcpy(lk, lnext, n * sizeof(float));
     }
     free(kept); free(Tk); free(Tw); free(mu); free(lnext);
+    return 0;
+}
+
+/* ------------------------------------------------------------ operators */
+/* The operators of the kernel notation in FP32 on the widened values of A
+ * (storage ST_F32 or a BF16 form; nz == 1: a 2-D field): op 0 the interior
+ * values, ops 1-3 the second difference (A[p] - A[c]) - (A[c] - A[m]) along
+ * x, y, z, op 4 the Laplacian (d2x*cx + d2y*cy) + d2z*cz with cx the FP32
+ * rounding of rdx*rdx formed in FP64 (2-D: d2x*cx + d2y*cy).  out holds the
+ * interior, x fastest. */
+int emul_apply32(int op, float* out, const void* A, int nx, int ny, int nz, double rdx, double rdy, double rdz,
+                 int storage)
+{
+    const int twod = nz == 1;
+    if (op < 0 || op > 4 || nx < 3 || ny < 3 || (!twod && nz < 3) || (twod && op == 3)) return -1;
+    if (storage != ST_F32 && storage != ST_BF16_SR && storage != ST_BF16_RNE) return -1;
+    const size_t n = (size_t)nx * ny * nz;
+    float* a = (float*)malloc(n * sizeof(float));
+    if (!a) return -2;
+    widen_field(a, A, n, storage);
+    const float cx = (float)(rdx * rdx), cy = (float)(rdy * rdy), cz = (float)(rdz * rdz);
+    const int z0 = twod ? 0 : 1, z1 = twod ? 1 : nz - 1;
+    size_t o = 0;
+    for (int iz = z0; iz < z1; ++iz)
+        for (int iy = 1; iy < ny - 1; ++iy)
+            for (int ix = 1; ix < nx - 1; ++ix) {
+                const float t = a[EIDX(ix, iy, iz)];
+                const float d2x = (a[EIDX(ix + 1, iy, iz)] - t) - (t - a[EIDX(ix - 1, iy, iz)]);
+                const float d2y = (a[EIDX(ix, iy + 1, iz)] - t) - (t - a[EIDX(ix, iy - 1, iz)]);
+                float d2z = 0.0f;
+                if (!twod) d2z = (a[EIDX(ix, iy, iz + 1)] - t) - (t - a[EIDX(ix, iy, iz - 1)]);
+                float v;
+                switch (op) {
+                case 0: v = t; break;
+                case 1: v = d2x; break;
+                case 2: v = d2y; break;
+                case 3: v = d2z; break;
+                default: v = twod ? d2x * cx + d2y * cy : (d2x * cx + d2y * cy) + d2z * cz; break;
+                }
+                out[o++] = v;
+            }
+    free(a);
     return 0;
 }

@@ -76,6 +76,7 @@ _SIGS = {
     "diff3d_philox4x32_10": ([_u32p, _u32p, _u32p], None),
     "diff2d_step": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _vp], _i),
     "diff2d_run": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _vp], _i),
+    "diff3d_apply": ([_i, _vp, _vp, _i, _i, _i, _d, _d, _d, _i, _vp], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -265,6 +266,63 @@ def run2d(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: f
     with _on(T):
         _check(_lib.diff2d_run(_p(T), _p(T2), _p(Ci), nx, ny, lam, dt, rdx, rdy, int(nt), _code(T), _stream(T)),
                "run2d")
+
+
+# Operators of the kernel notation (diff3d_op): interior selection, second
+# differences along x, y, z, and the weighted Laplacian of the step.
+OP_INN, OP_D2_XI, OP_D2_YI, OP_D2_ZI, OP_LAP = 0, 1, 2, 3, 4
+
+
+def apply(op: int, A: torch.Tensor, rdx: float = 1.0, rdy: float = 1.0, rdz: float = 1.0,
+          out: torch.Tensor | None = None) -> torch.Tensor:
+    """One finite-difference operator of Fig. 1's notation applied to the
+    field A, shape (nz, ny, nx) or (ny, nx) for a 2-D field: the values at
+    the interior points, each dimension two shorter, in the arithmetic type
+    (float64 for float64 fields, float32 for float32 and bfloat16 fields).
+    rdx, rdy, rdz (inverse spacings) enter OP_LAP only."""
+    if not isinstance(A, torch.Tensor) or not A.is_cuda or not A.is_contiguous():
+        raise ValueError("A must be a contiguous CUDA/HIP tensor")
+    if A.dim() == 3:
+        nz, ny, nx = A.shape
+    elif A.dim() == 2:
+        (ny, nx), nz = A.shape, 1
+    else:
+        raise ValueError("A must be a (nz, ny, nx) or (ny, nx) tensor")
+    odt = torch.float64 if A.dtype == torch.float64 else torch.float32
+    shape = tuple(n - 2 for n in A.shape)
+    if out is None:
+        out = torch.empty(shape, dtype=odt, device=A.device)
+    elif (not out.is_cuda or out.device != A.device or out.dtype != odt or tuple(out.shape) != shape
+          or not out.is_contiguous()):
+        raise ValueError("out must be a contiguous %s tensor of shape %s on A's device" % (odt, shape))
+    with _on(A):
+        _check(_lib.diff3d_apply(int(op), _p(out), _p(A), nx, ny, nz, rdx, rdy, rdz, _code(A), _stream(A)), "apply")
+    return out
+
+
+def inn(A: torch.Tensor) -> torch.Tensor:
+    """@inn(A): the interior values of A."""
+    return apply(OP_INN, A)
+
+
+def d2_xi(A: torch.Tensor) -> torch.Tensor:
+    """@d2_xi(A): second difference along x at the interior points."""
+    return apply(OP_D2_XI, A)
+
+
+def d2_yi(A: torch.Tensor) -> torch.Tensor:
+    """@d2_yi(A): second difference along y at the interior points."""
+    return apply(OP_D2_YI, A)
+
+
+def d2_zi(A: torch.Tensor) -> torch.Tensor:
+    """@d2_zi(A): second difference along z at the interior points (3-D only)."""
+    return apply(OP_D2_ZI, A)
+
+
+def laplacian(A: torch.Tensor, rdx: float, rdy: float, rdz: float = 1.0) -> torch.Tensor:
+    """(d2x*rdx^2 + d2y*rdy^2) + d2z*rdz^2 at the interior points (2-D: no z term)."""
+    return apply(OP_LAP, A, rdx, rdy, rdz)
 
 
 def step(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,

@@ -13,6 +13,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "fd_ops.hpp"
 
 namespace diff3d {
 
@@ -36,11 +37,7 @@ __device__ inline typename Traits<DT>::C lap7(typename Traits<DT>::C t, typename
                                               typename Traits<DT>::C yp, typename Traits<DT>::C zm,
                                               typename Traits<DT>::C zp, const AdjArgs<DT>& a)
 {
-    using C = typename Traits<DT>::C;
-    const C d2x = (xp - t) - (t - xm);
-    const C d2y = (yp - t) - (t - ym);
-    const C d2z = (zp - t) - (t - zm);
-    return (d2x * a.cx + d2y * a.cy) + d2z * a.cz;
+    return fd::lap3(t, xm, xp, ym, yp, zm, zp, a.cx, a.cy, a.cz);
 }
 
 // ------------------------------------------------------------------ naive

@@ -14,6 +14,7 @@
 #include "adjoint_launch.hpp"
 #include "diff2d_launch.hpp"
 #include "diff3d.h"
+#include "fd_apply.hpp"
 #include "forward_launch.hpp"
 #include "host_common.hpp"
 #include "util_launch.hpp"
@@ -444,6 +445,22 @@ int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, do
     }
     if (!rc && a != T) rc = copy_bytes(T, a, fb, st);
     return rc;
+}
+
+// ------------------------------------------------------------- operators
+
+int diff3d_apply(int op, void* out, const void* in, int nx, int ny, int nz, double rdx, double rdy, double rdz,
+                 int dtype, void* stream)
+{
+    if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
+    if (op < DIFF3D_OP_INN || op > DIFF3D_OP_LAP) return DIFF3D_EINVAL;
+    if (!out || !in || nx < 3 || ny < 3 || nz < 1 || nz == 2) return DIFF3D_EINVAL;
+    if (nz == 1 && op == DIFF3D_OP_D2_ZI) return DIFF3D_EINVAL;
+    if (npoints(nx, ny, nz) >= kMaxPoints) return DIFF3D_EINVAL;
+    const size_t ib = npoints(nx, ny, nz) * elem_size(dtype);
+    const size_t ob = npoints(nx - 2, ny - 2, nz == 1 ? 1 : nz - 2) * (dtype == DIFF3D_F64 ? 8 : 4);
+    if (overlap(out, ob, in, ib)) return DIFF3D_EINVAL;
+    return apply_dispatch(dtype, op, out, in, nx, ny, nz, rdx, rdy, rdz, as_stream(stream));
 }
 
 void diff3d_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])

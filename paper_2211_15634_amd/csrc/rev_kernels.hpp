@@ -14,6 +14,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "fd_ops.hpp"
 
 namespace diff3d {
 
@@ -46,8 +47,8 @@ struct RevArgs {
 // Lap(F_{S-j}) is formed 2j-2 iterations before level j uses it and waits in
 // a register ring.  x/y neighbours of F_f and mu_j come from their planes
 // staged in double-buffered LDS in the previous iteration (one barrier per
-// plane); z neighbours from registers.  Loads are issued one plane
-// iteration before the one that uses them, from addresses clamped into the
+// plane); z neighbours from registers.  Loads are issued one or two plane
+// iterations before the one that uses them, from addresses clamped into the
 // grid (values outside the grid are never used).
 template <int DT, int S, int W0, int H0, int NTH>
 __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, int zlen)
@@ -116,10 +117,7 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
         for (int k = 0; k < K; ++k) dst[k] = Tr::load(f[base[k] + zo]);
     };
     auto lap = [&](C t, C xm, C xp, C ym, C yp, C zm, C zp) __attribute__((always_inline)) -> C {
-        const C d2x = (xp - t) - (t - xm);
-        const C d2y = (yp - t) - (t - ym);
-        const C d2z = (zp - t) - (t - zm);
-        return (d2x * a.cx + d2y * a.cy) + d2z * a.cz;
+        return fd::lap3(t, xm, xp, ym, yp, zm, zp, a.cx, a.cy, a.cz);
     };
     auto stage = [&](C (&buf)[A0], const C (&src)[K]) __attribute__((always_inline)) {
 #pragma unroll
@@ -183,6 +181,11 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
     C mh[S][2][K];                                // mu_{j-1} at the two planes below the fresh one
     C g[S][K];                                    // gCi partial sum of the plane level j+1 works on
     C lt[2][K], lc[2][K], ll[2][K], lg[2][K];     // loads in flight: T, Ci, lambda, gCi
+    // FP64: lambda and gCi are loaded two plane iterations before their use
+    // (the waves otherwise wait on them: 256^3 reverse sweep 22.0 -> 20.8
+    // ms); FP32 at two points per thread would spill with the longer
+    // lifetimes (13.4 -> 14.6 ms) and keeps one iteration.
+    constexpr bool kFar = sizeof(C) == 8;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -213,16 +216,23 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
     load(a.Ci, p0 + 1, lc[0]);
     load(a.lin, p0 - S + 2, ll[0]);
     load_g(p0 - S + 1, lg[0]);
+    if constexpr (kFar) {
+        load(a.lin, p0 - S + 3, ll[1]);
+        load_g(p0 - S + 2, lg[1]);
+    }
     stage(lf[0][1], t0[1]);
 
     auto iteration = [&](auto par, int p) __attribute__((always_inline)) {
         constexpr int PAR = decltype(par)::value;
         constexpr int buf = PAR, rbuf = PAR ^ 1;
-        // loads for the next iteration
+        // T and Ci two iterations ahead; lambda and gCi one ahead (or two,
+        // issued below, with kFar)
         load(a.Tk, p + 3, lt[PAR ^ 1]);
         load(a.Ci, p + 2, lc[PAR ^ 1]);
-        load(a.lin, p - S + 3, ll[PAR ^ 1]);
-        load_g(p - S + 2, lg[PAR ^ 1]);
+        if constexpr (!kFar) {
+            load(a.lin, p - S + 3, ll[PAR ^ 1]);
+            load_g(p - S + 2, lg[PAR ^ 1]);
+        }
         lds_barrier();
         stage(lf[0][buf], t0[2]);                 // F_0 at p+1
 
@@ -246,7 +256,7 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
                     const int i = rr[k] * W0 + cc[k];
                     lp = lap(ce, lf[f - 1][rbuf][i - 1], lf[f - 1][rbuf][i + 1], lf[f - 1][rbuf][i - W0],
                              lf[f - 1][rbuf][i + W0], zm, zp);
-                    if (f < S) v = ce + a.dt * ((a.lam * cr[f - 1][k]) * lp);
+                    if (f < S) v = fd::update(ce, a.dt, a.lam * cr[f - 1][k], lp);
                 }
                 out[k] = v;
                 lpr[S - f][0][k] = lp;            // Lap(F_{f-1}) serves level j = S-f+1
@@ -279,6 +289,11 @@ __global__ __launch_bounds__(NTH) void rev_tbs(RevArgs<DT> a, int ntx, int nty, 
         // gCi of plane p-S+1 enters the partial sums
 #pragma unroll
         for (int k = 0; k < K; ++k) g[0][k] = lg[PAR][k];
+        if constexpr (kFar) {
+            // lambda and gCi two iterations ahead, into the slots just consumed
+            load(a.lin, p - S + 4, ll[PAR]);
+            load_g(p - S + 3, lg[PAR]);
+        }
 #pragma unroll
         for (int j = 1; j <= S; ++j) {
             const int z = p - S - j + 2;

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "fd_ops.hpp"
 
 namespace diff3d {
 
@@ -69,9 +70,8 @@ __global__ __launch_bounds__(64 * WPB) void step2d_ymarch(Step2dArgs<DT> a, int 
         if (lane == 0) xm = hc;
         if (lane == 63) xp = hc;
         const C t = rc;
-        const C d2x = (xp - t) - (t - xm);
-        const C d2y = (rp - t) - (t - rm);
-        const C w = t + a.dt * ((a.lam * cc) * (d2x * a.cx + d2y * a.cy));
+        const C l = fd::lap2(t, xm, xp, rm, rp, a.cx, a.cy);
+        const C w = fd::update(t, a.dt, a.lam * cc, l);
         if (interior_x) __builtin_nontemporal_store(Tr::store(w, 0), a.T2 + (size_t)x + sy * (size_t)y);
         rm = rc;
         rc = rp;

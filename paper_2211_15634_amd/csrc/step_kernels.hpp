@@ -2,13 +2,15 @@
 // (Fig. 1, `step!`): on interior points
 //   T2 = T + dt*((lam*Ci)*((d2x*cx + d2y*cy) + d2z*cz)),
 //   d2x = (T[x+1] - T[x]) - (T[x] - T[x-1])  (likewise y, z),
-// evaluated in this order with no contraction (the library is built with
-// -ffp-contract=off), so the FP64 form reproduces a plain loop bit for bit.
+// composed of the operators of fd_ops.hpp, evaluated in this order with no
+// contraction (the library is built with -ffp-contract=off), so the FP64
+// form reproduces a plain loop bit for bit.
 #pragma once
 
 #include <type_traits>
 
 #include "common.hpp"
+#include "fd_ops.hpp"
 
 namespace diff3d {
 
@@ -32,11 +34,8 @@ __device__ inline typename Traits<DT>::C stencil_point(typename Traits<DT>::C t,
                                                        typename Traits<DT>::C zp, typename Traits<DT>::C ci,
                                                        const StepArgs<DT>& a)
 {
-    using C = typename Traits<DT>::C;
-    const C d2x = (xp - t) - (t - xm);
-    const C d2y = (yp - t) - (t - ym);
-    const C d2z = (zp - t) - (t - zm);
-    return t + a.dt * ((a.lam * ci) * ((d2x * a.cx + d2y * a.cy) + d2z * a.cz));
+    const auto l = fd::lap3(t, xm, xp, ym, yp, zm, zp, a.cx, a.cy, a.cz);
+    return fd::update(t, a.dt, a.lam * ci, l);
 }
 
 // The same update with lam*Ci already formed (identical rounding).
@@ -47,11 +46,8 @@ __device__ inline typename Traits<DT>::C stencil_point_lc(typename Traits<DT>::C
                                                           typename Traits<DT>::C zp, typename Traits<DT>::C lamci,
                                                           const StepArgs<DT>& a)
 {
-    using C = typename Traits<DT>::C;
-    const C d2x = (xp - t) - (t - xm);
-    const C d2y = (yp - t) - (t - ym);
-    const C d2z = (zp - t) - (t - zm);
-    return t + a.dt * (lamci * ((d2x * a.cx + d2y * a.cy) + d2z * a.cz));
+    const auto l = fd::lap3(t, xm, xp, ym, yp, zm, zp, a.cx, a.cy, a.cz);
+    return fd::update(t, a.dt, lamci, l);
 }
 
 // ------------------------------------------------------------------ naive

@@ -392,3 +392,26 @@ def test_2d_argument_validation_without_gpu():
     assert lib.diff2d_run(p, q, r, 8, 8, *sc, -1, d3.F64, None) == d3.EINVAL
     assert lib.diff2d_run(p, q, p, 8, 8, *sc, 3, d3.F64, None) == d3.EINVAL
     assert lib.diff2d_run(p, q, r, 8, 8, *sc, 0, d3.F32, None) == d3.OK
+
+
+def test_apply_validation_without_gpu():
+    """diff3d_apply rejects bad operators, dtypes, sizes and overlaps before
+    any launch."""
+    lib = d3._lib
+    out = ctypes.c_void_p(1 << 31)
+    a = ctypes.c_void_p(4096)
+    rd = (1.0, 1.0, 1.0)
+    assert lib.diff3d_apply(d3.OP_D2_XI, out, a, 8, 8, 8, *rd, 9, None) == d3.EDTYPE
+    assert lib.diff3d_apply(-1, out, a, 8, 8, 8, *rd, d3.F64, None) == d3.EINVAL
+    assert lib.diff3d_apply(5, out, a, 8, 8, 8, *rd, d3.F64, None) == d3.EINVAL
+    assert lib.diff3d_apply(d3.OP_INN, None, a, 8, 8, 8, *rd, d3.F64, None) == d3.EINVAL
+    assert lib.diff3d_apply(d3.OP_INN, out, None, 8, 8, 8, *rd, d3.F64, None) == d3.EINVAL
+    for bad in ((2, 8, 8), (8, 2, 8), (8, 8, 2), (8, 8, 0), (8, 8, -3)):
+        assert lib.diff3d_apply(d3.OP_LAP, out, a, *bad, *rd, d3.F32, None) == d3.EINVAL
+    # no z axis in a 2-D field
+    assert lib.diff3d_apply(d3.OP_D2_ZI, out, a, 8, 8, 1, *rd, d3.F64, None) == d3.EINVAL
+    # out overlapping in (in: 8^3 doubles from 4096)
+    assert lib.diff3d_apply(d3.OP_INN, ctypes.c_void_p(4096 + 8 * 511), a, 8, 8, 8, *rd, d3.F64,
+                            None) == d3.EINVAL
+    assert lib.diff3d_apply(d3.OP_INN, a, a, 8, 8, 1, *rd, d3.BF16, None) == d3.EINVAL
+    assert lib.diff3d_apply(d3.OP_INN, out, a, 1 << 14, 1 << 14, 1 << 14, *rd, d3.F32, None) == d3.EINVAL
