@@ -93,14 +93,17 @@ def _counters(d):
     return out
 
 
-def summarize_traffic(fetch_dir, write_dir, kernel, steps, workload, nbytes_alg, out_prefix, command):
+def summarize_traffic(fetch_dir, write_dir, kernel, steps, workload, nbytes_alg, out_prefix, command,
+                      calibration=None, note="read T and Ci, write T2 once", max_rows=8):
     """FETCH_SIZE / WRITE_SIZE per dispatch (KiB) from two rocprofv3 --pmc runs
     of --traffic-probe, scaled by what each counter reads for the 1 GiB copy
-    launched first; writes <out_prefix>.json and .md."""
+    launched first (or in the runs named by `calibration`); writes
+    <out_prefix>.json and .md."""
     fetch = _counters(fetch_dir)["FETCH_SIZE"]
     write = _counters(write_dir)["WRITE_SIZE"]
-    cf = [v for _, n, v in fetch if "copy16" in n]
-    cw = [v for _, n, v in write if "copy16" in n]
+    cfd, cwd = calibration or (fetch_dir, write_dir)
+    cf = [v for _, n, v in _counters(cfd)["FETCH_SIZE"] if "copy16" in n]
+    cw = [v for _, n, v in _counters(cwd)["WRITE_SIZE"] if "copy16" in n]
     kf = [v for _, n, v in fetch if kernel in n]
     kw = [v for _, n, v in write if kernel in n]
     kname = next(n for _, n, _ in fetch if kernel in n).split("(")[0]
@@ -119,12 +122,15 @@ def summarize_traffic(fetch_dir, write_dir, kernel, steps, workload, nbytes_alg,
     with open(out_prefix + ".json", "w") as f:
         json.dump(rec, f, indent=1)
     lines = ["# HBM traffic of `%s`, %s" % (kname, workload), "",
-             "One launch advances %d time step(s).  Compulsory bytes per launch (read T and Ci, write T2 once): "
-             "%d B." % (steps, nbytes_alg), "", "Commands (repository root, one MI355X):", "", "```", command, "```",
-             "", "| dispatch | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |", "|---|---|---|"]
+             "One launch advances %d time step(s).  Compulsory bytes per launch (%s): "
+             "%d B." % (steps, note, nbytes_alg), "", "Commands (repository root, one MI355X):", "", "```", command,
+             "```", "", "| dispatch | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |", "|---|---|---|"]
     for i, (x, y) in enumerate(zip(cf, cw)):
         lines.append("| copy16, 1 GiB, #%d | %.1f | %.1f |" % (i + 1, x, y))
     for i, (x, y) in enumerate(zip(kf, kw)):
+        if i == max_rows:
+            lines.append("| ... %d more dispatches | | |" % (len(kf) - max_rows))
+            break
         lines.append("| kernel #%d | %.1f | %.1f |" % (i + 1, x, y))
     lines += ["", "Calibration with the copy of known size (1 GiB read and written): FETCH_SIZE reports %.5f of "
               "the bytes read, WRITE_SIZE %.5f of the bytes written.  Scaled, per launch (median):" % (fs, ws), "",
@@ -136,10 +142,13 @@ def summarize_traffic(fetch_dir, write_dir, kernel, steps, workload, nbytes_alg,
     print(json.dumps(rec))
 
 
-def summarize_trace(trace_dir, out_md, command, top=14):
+def summarize_trace(trace_dir, out_md, command, top=14, title="", note=""):
     rows = _db_rows(trace_dir, "select name, total_calls, total_duration, average, percentage from top_kernels")
-    lines = ["# rocprofv3 kernel trace summary", "", "Command (repository root, one MI355X):", "", "```", command,
-             "```", "", "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    lines = ["# rocprofv3 kernel trace summary" + (": " + title if title else ""), ""]
+    if note:
+        lines += [note, ""]
+    lines += ["Command (repository root, one MI355X):", "", "```", command,
+              "```", "", "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
     rows.sort(key=lambda r: -float(r[2]))
     for name, calls, total, avg, pct in rows[:top]:
         lines.append("| `%s` | %s | %.1f | %.2f | %.2f |" % (name.split("(")[0][:120], calls, float(total),
@@ -252,16 +261,21 @@ def main():
     ap.add_argument("--workload", default="bump512_f64")
     ap.add_argument("--steps-per-launch", type=int, default=4)
     ap.add_argument("--compulsory-bytes", type=float, default=3 * 8 * 512 ** 3)
+    ap.add_argument("--calibration", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="counter runs holding the 1 GiB copy (default: the summarized runs)")
+    ap.add_argument("--compulsory-note", default="read T and Ci, write T2 once")
+    ap.add_argument("--note", default="", help="a paragraph under the title of a trace summary")
     ap.add_argument("--out", default=None)
     ap.add_argument("--command", default="")
     args = ap.parse_args()
 
     if args.summarize_traffic:
         summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1], args.kernel, args.steps_per_launch,
-                          args.workload, int(args.compulsory_bytes), args.out, args.command)
+                          args.workload, int(args.compulsory_bytes), args.out, args.command,
+                          calibration=args.calibration, note=args.compulsory_note)
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.out, args.command)
+        summarize_trace(args.summarize_trace, args.out, args.command, title=args.title, note=args.note)
         return
     if args.summarize_sq:
         summarize_sq(args.summarize_sq[0], args.summarize_sq[1], args.kernel, args.title, args.out, args.command)

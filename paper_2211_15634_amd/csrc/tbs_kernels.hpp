@@ -32,23 +32,23 @@ namespace diff3d {
 // VGPRs, two workgroups per CU; its LDS allows it): round to nearest fits
 // without spills, and four-step passes at 512^3 take 100 us per step against
 // 147 us at one workgroup per CU (two-step passes: 136 us); stochastic
-// rounding fits with its raw-value rings, 144 us per step (one workgroup
+// rounding fits with its raw-value rings, 136 us per step (one workgroup
 // per CU: 174 us).
 // The value of the next (UP) or previous lane of the wave (DPP wave shift by
-// one lane; the end lanes get their own value back, unused: the region's
-// outermost columns are never updated).
+// one lane; the end lanes read zero, unused: the region's outermost columns
+// are never updated).
 template <class T, bool UP>
 __device__ inline T lane_shift(T v)
 {
     constexpr int ctrl = UP ? 0x130 : 0x138;     // wave_shl:1 / wave_shr:1
     if constexpr (sizeof(T) == 8) {
         const int2 w = __builtin_bit_cast(int2, v);
-        const int lo = __builtin_amdgcn_update_dpp(w.x, w.x, ctrl, 0xF, 0xF, false);
-        const int hi = __builtin_amdgcn_update_dpp(w.y, w.y, ctrl, 0xF, 0xF, false);
+        const int lo = __builtin_amdgcn_mov_dpp(w.x, ctrl, 0xF, 0xF, true);
+        const int hi = __builtin_amdgcn_mov_dpp(w.y, ctrl, 0xF, 0xF, true);
         return __builtin_bit_cast(T, int2{lo, hi});
     } else {
         const int w = __builtin_bit_cast(int, v);
-        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(w, w, ctrl, 0xF, 0xF, false));
+        return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(w, ctrl, 0xF, 0xF, true));
     }
 }
 
@@ -68,17 +68,22 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     constexpr int TX = W0 - 2 * S, TY = H0 - 2 * S, A0 = W0 * H0;
     static_assert(TX > 0 && TY > 0, "region too small for S steps");
     constexpr int K = (A0 + NTH - 1) / NTH;       // region points per thread
-    __shared__ C lds[S][2][H0][W0];               // levels 0 .. S-1, double-buffered
+    // levels 0 .. S-1, double-buffered; region row r is array row r + 1
+    __shared__ C lds[S][2][H0 + 2][W0];
     // Stochastic rounding of the stored level: the 64 points a wave holds
     // for one point slot k are consecutive in x, so they lie in at most 9
     // Philox blocks of 8 consecutive points; a wave evaluates all 9*K blocks
     // it needs in one Philox call (one block per lane) per plane iteration
     // and passes the words through LDS.  Without room for them every lane
     // draws its own block.
+    // With lanes to spare, one call covers the planes of two consecutive
+    // iterations (NP = 2: half the Philox evaluations; BF16 four-step passes
+    // at 512^3 143 -> 136 us per step).
     constexpr int NB = 9;
     constexpr bool SR_BATCH = Tr::sr && NB * K <= 64;
+    constexpr int NP = (SR_BATCH && 2 * NB * K <= 64) ? 2 : 1;
     constexpr int NWAVE = NTH / 64;
-    __shared__ uint32_t srw[SR_BATCH ? NWAVE : 1][SR_BATCH ? NB * K : 1][4];
+    __shared__ uint32_t srw[SR_BATCH ? NWAVE : 1][SR_BATCH ? NP * NB * K : 1][4];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
@@ -134,6 +139,11 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     // x neighbours by cross-lane moves: FP64 and FP32 with W0 = 64 (1.5%
     // faster at 512^3; the BF16 kernels, at 64 VGPRs, are slower with them)
     constexpr bool kLaneX = W0 == 64 && (DT == DIFF3D_F64 || DT == DIFF3D_F32);
+    // Branch-free levels for FP64 (512^3 four-step passes 225 -> 217 us per
+    // step); FP32 and BF16 run 2-8% slower that way and keep the per-level
+    // tests.
+    constexpr bool kFlat = DT == DIFF3D_F64;
+    static_assert(!kFlat || kLaneX, "branch-free levels take x neighbours by cross-lane moves");
     bool act[S + 1][K];
 #pragma unroll
     for (int s = 1; s <= S; ++s)
@@ -141,6 +151,18 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
         for (int k = 0; k < K; ++k)
             act[s][k] = live[k] & ((rr[k] >= s) | ey0) & ((rr[k] < H0 - s) | ey1) & ((cc[k] >= s) | ex0) &
                         ((cc[k] < W0 - s) | ex1) & (gx[k] >= 1) & (gx[k] <= nx - 2) & (gy[k] >= 1) & (gy[k] <= ny - 2);
+    // Branch-free levels: every lane computes every level, and the result is
+    // kept only at interior grid points (elsewhere the level keeps the
+    // input's value: the fixed boundary).  Points of a level outside that
+    // level's region get values that no needed point reads (a level-s point
+    // reads level s-1 only within distance one), so no per-level region
+    // test is needed.  The staged planes carry one spare row above and below
+    // the region (never written), so that the neighbour reads of the
+    // region's outermost rows and columns stay inside the array; what they
+    // read there is never used.
+    bool ixy[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) ixy[k] = live[k] && interior_xy(k);
     bool otile[K];                                // on this workgroup's output tile
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -174,7 +196,7 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     auto stage = [&](int lev, int buf, const C (&src)[K]) __attribute__((always_inline)) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (live[k]) lds[lev][buf][rr[k]][cc[k]] = src[k];
+            if (live[k]) lds[lev][buf][rr[k] + 1][cc[k]] = src[k];
     };
 
     // Registers: level-0 planes p-1 .. p+1; for levels 1 .. S-1 the two
@@ -251,28 +273,33 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     // consecutive in memory, from index i0 (lane 0's); lane l's point is
     // i0 + l, in block (i0 % 8 + l) / 8 after lane 0's, at position
     // (i0 % 8 + l) % 8.  Only i0 % 8 (wave-uniform) is kept per slot.
-    int i0mod[SR_BATCH ? K : 1];
+    int i0mod[NP][SR_BATCH ? K : 1];
     auto draw = [&](int p) __attribute__((always_inline)) {
         if constexpr (SR_BATCH) {
             const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
-            const int z = p - S + 1;             // the plane level S reaches in this iteration
-            size_t g0[K];
+            size_t g0[NP][K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const size_t i0 = gidx(k, z) - (size_t)lane;
-                const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)i0);
-                const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(i0 >> 32));
-                const size_t u = ((size_t)hi << 32) | lo;
-                g0[k] = u >> 3;
-                i0mod[k] = (int)(lo & 7u);
+            for (int q = 0; q < NP; ++q) {
+                const int z = p + q - S + 1;     // the plane level S reaches in iteration p + q
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const size_t i0 = gidx(k, z) - (size_t)lane;
+                    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)i0);
+                    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(i0 >> 32));
+                    const size_t u = ((size_t)hi << 32) | lo;
+                    g0[q][k] = u >> 3;
+                    i0mod[q][k] = (int)(lo & 7u);
+                }
             }
-            // lane L computes block b of slot k, L = k*NB + b
-            if (lane < NB * K) {
-                const int kk = lane / NB, b = lane % NB;
+            // lane L computes block b of slot k for plane q, L = (q*K + k)*NB + b
+            if (lane < NP * NB * K) {
+                const int qk = lane / NB, b = lane % NB;
                 size_t g = 0;
 #pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (kk == k) g = g0[k] + (size_t)b;
+                for (int q = 0; q < NP; ++q)
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        if (qk == q * K + k) g = g0[q][k] + (size_t)b;
                 const u32x4 r = sr_block(a.sr, g);
                 srw[wv][lane][0] = r.x;
                 srw[wv][lane][1] = r.y;
@@ -282,12 +309,13 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
             __builtin_amdgcn_wave_barrier();   // the wave's LDS writes precede its reads (in order per wave)
         }
     };
-    auto rounding_at = [&](int k, int z) __attribute__((always_inline)) -> uint32_t {
+    // q: which of the draw's planes (the iteration's parity when NP = 2)
+    auto rounding_at = [&](int k, int z, int q) __attribute__((always_inline)) -> uint32_t {
         if constexpr (SR_BATCH) {
             const int wv = (int)(threadIdx.x >> 6);
-            const int off = i0mod[k] + (int)(threadIdx.x & 63);
+            const int off = i0mod[q][k] + (int)(threadIdx.x & 63);
             const int j = off & 7;
-            const uint32_t w = srw[wv][k * NB + (off >> 3)][j >> 1];
+            const uint32_t w = srw[wv][(q * K + k) * NB + (off >> 3)][j >> 1];
             return (j & 1) ? (w & 0xFFFF0000u) : (w << 16);
         } else {
             return rounding(gidx(k, z));
@@ -298,7 +326,7 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     auto iteration = [&](auto par, int p) __attribute__((always_inline)) {
         constexpr int PAR = decltype(par)::value;
         constexpr int buf = PAR, rbuf = PAR ^ 1;
-        draw(p);
+        if (NP == 1 || PAR == 0) draw(p);
         // 1. loads two planes ahead
         if constexpr (PK) {
             load_pairs(a.T, base, p + 3, ltp[PAR ^ 1]);
@@ -319,6 +347,36 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
             const int z = p - s + 1;
             const bool zact = z >= zb - (S - s) && z < ze + (S - s) && z >= 1 && z <= nz - 2;
             C out[K];
+            if constexpr (kFlat) {
+                const bool zin = z >= 1 && z <= nz - 2;
+                const bool zout = z >= zb && z < ze;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const C zm = s == 1 ? t0[0][k] : u[s - 2][0][k];
+                    const C ce = s == 1 ? t0[1][k] : u[s - 2][1][k];
+                    const C zp = prev[k];
+                    C xm, xp;
+                    if constexpr (kLaneX) {
+                        xm = lane_shift<C, false>(ce);
+                        xp = lane_shift<C, true>(ce);
+                    } else {
+                        xm = (&lds[s - 1][rbuf][rr[k] + 1][0])[cc[k] - 1];
+                        xp = (&lds[s - 1][rbuf][rr[k] + 1][0])[cc[k] + 1];
+                    }
+                    const C ym = lds[s - 1][rbuf][rr[k]][cc[k]];
+                    const C yp = lds[s - 1][rbuf][rr[k] + 2][cc[k]];
+                    const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, lamci(s, k), a);
+                    if (s < S) {
+                        out[k] = (zin && ixy[k]) ? w : ce;
+                    } else if (zout && otile[k]) {
+                        const S_ o = Tr::store(w, rounding_at(k, z, NP == 2 ? PAR : 0));
+                        if (NT)
+                            __builtin_nontemporal_store(o, a.T2 + gidx(k, z));
+                        else
+                            a.T2[gidx(k, z)] = o;
+                    }
+                }
+            } else
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 // level s-1 at planes z-1, z, z+1 for this point
@@ -335,17 +393,17 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
                     xpd = lane_shift<C, true>(ce);
                 }
                 if (zact && (kMaskTable ? act[s][k] : in_level(k, s) && interior_xy(k))) {
-                    const C xm = kLaneX ? xmd : lds[s - 1][rbuf][rr[k]][cc[k] - 1];
-                    const C xp = kLaneX ? xpd : lds[s - 1][rbuf][rr[k]][cc[k] + 1];
-                    const C ym = lds[s - 1][rbuf][rr[k] - 1][cc[k]];
-                    const C yp = lds[s - 1][rbuf][rr[k] + 1][cc[k]];
+                    const C xm = kLaneX ? xmd : lds[s - 1][rbuf][rr[k] + 1][cc[k] - 1];
+                    const C xp = kLaneX ? xpd : lds[s - 1][rbuf][rr[k] + 1][cc[k] + 1];
+                    const C ym = lds[s - 1][rbuf][rr[k]][cc[k]];
+                    const C yp = lds[s - 1][rbuf][rr[k] + 2][cc[k]];
                     const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, lamci(s, k), a);
                     if (s < S) {
                         v = w;
                     } else if (z >= zb && z < ze &&
                                (kMaskTable ? otile[k]
                                            : gx[k] >= ox0 && gx[k] < ox1 && gy[k] >= oy0 && gy[k] < oy1)) {
-                        const S_ o = Tr::store(w, rounding_at(k, z));
+                        const S_ o = Tr::store(w, rounding_at(k, z, NP == 2 ? PAR : 0));
                         if (NT)
                             __builtin_nontemporal_store(o, a.T2 + gidx(k, z));
                         else
@@ -368,7 +426,7 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
                 for (int k = 0; k < K; ++k) prev[k] = out[k];
             }
         }
-        if constexpr (SR_BATCH) __builtin_amdgcn_wave_barrier();   // reads done before the next draw writes
+        if constexpr (SR_BATCH) __builtin_amdgcn_wave_barrier();   // reads done before a later draw writes
         // 4. shift level 0 and Ci; the older slot (plane p+2, Ci plane p+1) enters
 #pragma unroll
         for (int k = 0; k < K; ++k) {
