@@ -59,10 +59,10 @@ typedef enum {
 
 typedef enum {
     DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps; in
-                                  diff3d_run S-step passes (S = 4 for FP64 and both BF16
-                                  forms; FP32: S = 4, 3 on x-y planes above 768^2
-                                  points); in diff3d_adjoint_run fused three-step
-                                  reverse passes */
+                                  diff3d_run S-step passes (S = 4 for both BF16 forms;
+                                  FP64: S = 4, 3 on x-y planes of at most 128^2 points;
+                                  FP32: S = 4, 3 on x-y planes above 768^2 points); in
+                                  diff3d_adjoint_run fused three-step reverse passes */
     DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */
     DIFF3D_KERNEL_ZMARCH = 2,  /* x-y tiles marching along z, planes in registers and LDS */
     DIFF3D_KERNEL_TB2 = 3,     /* diff3d_run: two steps per pass (temporal blocking), z-march

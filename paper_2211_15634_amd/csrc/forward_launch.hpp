@@ -359,11 +359,17 @@ int pass_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, in
 // (us per step, S = 3 / S = 4: 512^2 138 / 135, 768^2 497 / 461,
 // 896^2 732 / 755, 1024^2 1101 / 1410): three steps above 768^2 points.
 constexpr size_t kF32FourStepMaxPlane = (size_t)768 * 768;
+// FP64 on small grids, where a launch holds few workgroups and each z-chunk
+// is short, is faster with three-step passes (us per step, S = 3 / S = 4:
+// 64^3 3.78 / 4.27, 128^3 7.68 / 8.70; 192^3 16.8 / 16.1): three steps on
+// x-y planes of at most 128^2 points.
+constexpr size_t kF64ThreeStepMaxPlane = (size_t)128 * 128;
 
 int tbs_default_steps(int dtype, int nx, int ny)
 {
     switch (dtype) {
-    case DIFF3D_F64: return TbsDefaults<DIFF3D_F64>::S;
+    case DIFF3D_F64:
+        return (size_t)nx * (size_t)ny <= kF64ThreeStepMaxPlane ? 3 : TbsDefaults<DIFF3D_F64>::S;
     case DIFF3D_F32:
         return (size_t)nx * (size_t)ny > kF32FourStepMaxPlane ? 3 : TbsDefaults<DIFF3D_F32>::S;
     case DIFF3D_BF16: return TbsDefaults<DIFF3D_BF16>::S;

@@ -179,7 +179,7 @@ def test_config_validation():
         assert L.diff3d_pass_plan(64, 64, 64, 10, 0, d3.F64, ctypes.byref(raw), None, 0) == d3.EINVAL
     # the same override is instantiated for one storage size and not another
     c = d3.Config(zmarch=d3.Tile(p=(1, 8, 4, 0)))
-    assert L.diff3d_pass_plan(64, 64, 64, 10, 0, d3.F64, d3._ccfg(c), None, 0) == 3
+    assert L.diff3d_pass_plan(64, 64, 64, 10, 0, d3.F64, d3._ccfg(c), None, 0) == 4   # 3, 3, 2, 2
     assert L.diff3d_pass_plan(64, 64, 64, 10, 0, d3.F32, d3._ccfg(c), None, 0) == d3.EINVAL
     # reverse-only overrides: checked where they are used
     for c in (d3.Config(adj=d3.Tile(p=(3, 3, 3, 0))), d3.Config(rev=d3.Tile(p=(64, 16, 1024, 0))),
@@ -221,10 +221,14 @@ def test_pass_plan_rules():
             cfg = d3.Config(kernel=d3.KERNEL_TBS, pass_steps=S)
             assert _plan((9, 9, 9), nt, f64, C, cfg) == expect(nt, C, S, False), (nt, C, S)
             assert sum(_plan((9, 9, 9), nt, f64, C, cfg)) == nt
-        assert _plan((9, 9, 9), nt, f64, C) == expect(nt, C, 4, True), (nt, C)
+        assert _plan((9, 9, 9), nt, f64, C) == expect(nt, C, 3, True), (nt, C)
+        assert _plan((9, 129, 128), nt, f64, C) == expect(nt, C, 4, True), (nt, C)
         assert _plan((9, 9, 9), nt, f64, C, d3.Config(kernel=d3.KERNEL_ZMARCH)) == [1] * nt
         assert _plan((9, 9, 9), nt, f64, C, d3.Config(kernel=d3.KERNEL_TB2)) == expect(nt, C, 2, True)
-    # FP32 takes three-step passes on planes above 768^2 points
+    # FP64 takes three-step passes on planes of at most 128^2 points, FP32
+    # on planes above 768^2 points
+    assert set(_plan((4, 128, 128), 12, f64)) == {3}
+    assert set(_plan((4, 129, 128), 12, f64)) == {4}
     assert set(_plan((4, 769, 768), 12, torch.float32)) == {3}
     assert set(_plan((4, 768, 768), 12, torch.float32)) == {4}
     L = d3._lib
