@@ -35,6 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
+FP64_VECTOR_OPS_PEAK = 39.3     # Top/s: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz (add or multiply)
+ALU_OPS_PER_POINT_STEP = 18     # the step's FP operations per interior point: Laplacian 14, update 4
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "traffic_step_tbs4_bump512_f64.json")
 METRIC = "T_eff GB/s (% HBM peak) per 3-D diffusion step; adjoint/forward time ratio"
@@ -431,7 +433,16 @@ def main():
                 "hbm_GBps": round(hbm, 1) if hbm else None,
                 "frac_physical": round(hbm / HBM_PEAK_GBPS, 4) if hbm else None,
                 "teff_over_peak": round(PASS * compulsory / (kS_ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
-                "traffic_source_hash": tr_hash}
+                "traffic_source_hash": tr_hash,
+                # the FP64 vector-arithmetic roof beside the bandwidth one: the
+                # step's 18 operations per point (no fused multiply-add), S
+                # steps per launch, against 256 CUs x 4 SIMDs x 16 FP64 lanes x
+                # 2.4 GHz = 39.3 Top/s (78.6 TFLOP/s counts an FMA as two)
+                "alu": {"ops_per_point_step": ALU_OPS_PER_POINT_STEP,
+                        "achieved": round(ALU_OPS_PER_POINT_STEP * (n - 2) ** 3 * PASS / (kS_ms / 1e3) / 1e12, 2),
+                        "peak": FP64_VECTOR_OPS_PEAK, "unit": "Top/s",
+                        "frac": round(ALU_OPS_PER_POINT_STEP * (n - 2) ** 3 * PASS / (kS_ms / 1e3) / 1e12
+                                      / FP64_VECTOR_OPS_PEAK, 4)}}
     single = {"kernel": "step_zmarch (one step per launch)", "kernel_avg_us": round(k1_ms * 1e3, 2),
               "teff_GBps": round(bytes_step / (k1_ms / 1e3) / 1e9, 1)}
     two = {"kernel": "step_tb2 (two steps per launch)", "kernel_avg_us": round(k2_ms * 1e3, 2),
