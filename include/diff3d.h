@@ -285,8 +285,20 @@ int diff3d_copy(void* dst, const void* src, size_t bytes, void* stream);
 int diff2d_step(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt,
                 double rdx, double rdy, int dtype, void* stream);
 
+/* nsteps steps of the 2-D form in one pass over memory (1 <= nsteps <=
+ * DIFF2D_MAX_PASS_STEPS): the interior of T2 receives the state nsteps steps
+ * after T, bit-identical to nsteps single steps (intermediate states are
+ * kept in the storage type's arithmetic on chip).  Precondition: T2's
+ * boundary equals T's.  Same argument rules as diff2d_step; nsteps out of
+ * range is EINVAL. */
+#define DIFF2D_MAX_PASS_STEPS 8
+int diff2d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
+                 double rdy, int nsteps, int dtype, void* stream);
+
 /* nt steps of the 2-D form with the buffer swap: T2 = copy(T) first, then
- * T -> T2 -> T ...; the result T_nt is left in T (T2 is scratch).  Same
+ * passes of several steps each (diff2d_stepn; near-equal lengths of at most
+ * 7 steps for FP64 and 8 for FP32) alternating T -> T2 -> T ...; the result
+ * T_nt is left in T (T2 is scratch), bit-identical to nt single steps.  Same
  * argument rules as diff2d_step, plus nt >= 0 and T not overlapping Ci;
  * nt = 0 leaves T unchanged. */
 int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, double dt, double rdx,

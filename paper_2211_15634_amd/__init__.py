@@ -76,6 +76,7 @@ _SIGS = {
     "diff3d_philox4x32_10": ([_u32p, _u32p, _u32p], None),
     "diff2d_step": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _vp], _i),
     "diff2d_run": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _vp], _i),
+    "diff2d_stepn": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _vp], _i),
     "diff3d_apply": ([_i, _vp, _vp, _i, _i, _i, _d, _d, _d, _i, _vp], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -254,6 +255,19 @@ def step2d(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: 
     ny, nx = T.shape
     with _on(T):
         _check(_lib.diff2d_step(_p(T2), _p(T), _p(Ci), nx, ny, lam, dt, rdx, rdy, _code(T), _stream(T)), "step2d")
+
+
+def stepn2d(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
+            nsteps: int) -> None:
+    """nsteps steps of the 2-D form in one pass: interior of T2 = the state
+    nsteps steps after T (T2's boundary untouched)."""
+    _field2d(T, "T")
+    _field2d(T2, "T2", T)
+    _field2d(Ci, "Ci", T)
+    ny, nx = T.shape
+    with _on(T):
+        _check(_lib.diff2d_stepn(_p(T2), _p(T), _p(Ci), nx, ny, lam, dt, rdx, rdy, int(nsteps), _code(T), _stream(T)),
+               "stepn2d")
 
 
 def run2d(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,

@@ -425,6 +425,15 @@ int diff2d_step(void* T2, const void* T, const void* Ci, int nx, int ny, double 
     return step2d_dispatch(dtype, T2, T, Ci, nx, ny, lam, dt, rdx, rdy, as_stream(stream));
 }
 
+int diff2d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
+                 double rdy, int nsteps, int dtype, void* stream)
+{
+    const int rc = check2d(T2, T, Ci, nx, ny, dtype);
+    if (rc) return rc;
+    if (nsteps < 1 || nsteps > kMaxSteps2d) return DIFF3D_EINVAL;
+    return step2dn_dispatch(dtype, nsteps, T2, T, Ci, nx, ny, lam, dt, rdx, rdy, as_stream(stream));
+}
+
 int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, double dt, double rdx, double rdy,
                int nt, int dtype, void* stream)
 {
@@ -435,10 +444,15 @@ int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, do
     if (nt == 0) return DIFF3D_OK;
     hipStream_t st = as_stream(stream);
     rc = copy_bytes(T2, T, fb, st);               // T2 = copy(T): both buffers carry T's boundary
+    // passes of near-equal length, at most P steps each, ping-ponging
+    const int P = run2d_pass_steps(dtype);
+    const int m = (nt + P - 1) / P;
     void* a = T;
     void* b = T2;
-    for (int it = 0; it < nt && !rc; ++it) {
-        rc = step2d_dispatch(dtype, b, a, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    for (int i = 0, done = 0; i < m && !rc; ++i) {
+        const int n = (nt - done + (m - i) - 1) / (m - i);
+        rc = step2dn_dispatch(dtype, n, b, a, Ci, nx, ny, lam, dt, rdx, rdy, st);
+        done += n;
         void* s = a;
         a = b;
         b = s;

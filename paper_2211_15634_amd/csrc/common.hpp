@@ -173,6 +173,23 @@ __device__ inline unsigned xcd_remap(unsigned b, unsigned nb)
     return xcd * per + (xcd < rem ? xcd : rem) + j;
 }
 
+// The value of the next (UP) or previous lane of the wave (DPP wave shift by
+// one lane; the end lanes read zero).
+template <class T, bool UP>
+__device__ inline T lane_shift(T v)
+{
+    constexpr int ctrl = UP ? 0x130 : 0x138;     // wave_shl:1 / wave_shr:1
+    if constexpr (sizeof(T) == 8) {
+        const int2 w = __builtin_bit_cast(int2, v);
+        const int lo = __builtin_amdgcn_mov_dpp(w.x, ctrl, 0xF, 0xF, true);
+        const int hi = __builtin_amdgcn_mov_dpp(w.y, ctrl, 0xF, 0xF, true);
+        return __builtin_bit_cast(T, int2{lo, hi});
+    } else {
+        const int w = __builtin_bit_cast(int, v);
+        return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(w, ctrl, 0xF, 0xF, true));
+    }
+}
+
 // LDS-only workgroup barrier: waits for this wave's LDS traffic and meets
 // the other waves, without waiting for outstanding global loads (those are
 // software-pipelined across the barrier).

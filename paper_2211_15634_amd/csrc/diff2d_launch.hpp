@@ -45,6 +45,82 @@ int launch_step2d(void* T2, const void* T, const void* Ci, int nx, int ny, doubl
     return hip_status();
 }
 
+// S steps in one pass (2 <= S <= kMaxSteps2d): regions of 64 points every
+// 64 - 2S along x, chunks of rows along y long enough that the 2S - 2 rows
+// of warm-up per chunk stay a small part of a wave's work.  The chunk count
+// aims at 64 waves per CU (us per step at S = 7 FP64 / 8 FP32, targets of
+// 16 / 32 / 64 / 128 waves per CU: 8192^2 81.0 / 73.9 / 75.9 / 75.4 and
+// 47.6 / 43.7 / 42.9 / 42.1; 16384^2 329.7 / 290.6 / 274.8 / 276.0 and
+// 180.9 / 163.9 / 151.7 / 152.0).
+constexpr int kStep2dMinRowsPerWarmup = 8;        // chunk rows >= 8 x (2S - 2)
+constexpr int kStep2dWavesPerCU = 64;             // waves per CU the chunk count aims at
+
+// Steps per pass of diff2d_run (us per step at 8192^2 for S = 1 / 4 / 6 / 7 /
+// 8: FP64 282 / 112 / 77 / 74 / 78, FP32 146 / 62 / 44 / 43 / 45; at 16384^2
+// FP32 S = 8 beats S = 7 by 6%).
+inline int run2d_pass_steps(int dtype)
+{
+    return dtype == DIFF3D_F64 ? 7 : 8;
+}
+
+template <int DT, int S>
+int launch_step2d_s(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
+                    double rdy, hipStream_t st)
+{
+    using Sz = typename Traits<DT>::S;
+    using C = typename Traits<DT>::C;
+    Step2dArgs<DT> a;
+    a.T2 = static_cast<Sz*>(T2);
+    a.T = static_cast<const Sz*>(T);
+    a.Ci = static_cast<const Sz*>(Ci);
+    a.nx = nx;
+    a.ny = ny;
+    a.lam = (C)lam;
+    a.dt = (C)dt;
+    a.cx = (C)(rdx * rdx);
+    a.cy = (C)(rdy * rdy);
+    constexpr int TX = 64 - 2 * S;
+    const int nstrips = nx <= 64 ? 1 : (nx - 64 + TX - 1) / TX + 1;
+    const int rows = ny - 2;
+    const int want = (256 * kStep2dWavesPerCU + nstrips - 1) / nstrips;
+    const int minlen = kStep2dMinRowsPerWarmup * (2 * S - 2);
+    const int nchunks = max(1, min(want, (rows + minlen - 1) / minlen));
+    int ylen = (rows + nchunks - 1) / nchunks;
+    if (ylen > 1) ylen |= 1;                      // chunk starts not a power of two rows apart
+    const long waves = (long)nstrips * nchunks;
+    const unsigned blocks = (unsigned)((waves + kStep2dWaves - 1) / kStep2dWaves);
+    step2d_ymarch_s<DT, S, kStep2dWaves><<<blocks, 64 * kStep2dWaves, 0, st>>>(a, nstrips, nchunks, ylen);
+    return hip_status();
+}
+
+template <int DT>
+int launch_step2d_n(int n, void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt,
+                    double rdx, double rdy, hipStream_t st)
+{
+    switch (n) {
+    case 1: return launch_step2d<DT>(T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    case 2: return launch_step2d_s<DT, 2>(T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    case 3: return launch_step2d_s<DT, 3>(T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    case 4: return launch_step2d_s<DT, 4>(T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    case 5: return launch_step2d_s<DT, 5>(T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    case 6: return launch_step2d_s<DT, 6>(T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    case 7: return launch_step2d_s<DT, 7>(T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    case 8: return launch_step2d_s<DT, 8>(T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    default: return DIFF3D_EINVAL;
+    }
+}
+
+// n steps (1 <= n <= kMaxSteps2d) in one pass of the 2-D form.
+int step2dn_dispatch(int dtype, int n, void* T2, const void* T, const void* Ci, int nx, int ny, double lam,
+                     double dt, double rdx, double rdy, hipStream_t st)
+{
+    switch (dtype) {
+    case DIFF3D_F64: return launch_step2d_n<DIFF3D_F64>(n, T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    case DIFF3D_F32: return launch_step2d_n<DIFF3D_F32>(n, T2, T, Ci, nx, ny, lam, dt, rdx, rdy, st);
+    default: return DIFF3D_EDTYPE;
+    }
+}
+
 int step2d_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt,
                     double rdx, double rdy, hipStream_t st)
 {

@@ -84,4 +84,91 @@ __global__ __launch_bounds__(64 * WPB) void step2d_ymarch(Step2dArgs<DT> a, int 
     }
 }
 
+// S steps per pass over HBM (S = 2 .. kMaxSteps2d).  A wave owns a region
+// of 64 consecutive x points (origin strip * (64 - 2S): regions start at the
+// grid's edge and the last one reaches its far edge) and marches along y
+// over the output rows of its chunk.  Level s (s = 0 .. S, level 0 = T^k) is
+// computed on the region's lanes s .. 63-s (a side on the grid's boundary
+// does not shrink: the boundary values are the same at every level), at row
+// y + 1 - s in iteration y, from level s-1 at rows y - s .. y + 2 - s: the
+// two older rows in registers, the newest just computed; x neighbours are
+// the adjacent lanes' values.  Every lane computes every level and keeps
+// the result only at interior grid points (elsewhere the level keeps the
+// fixed boundary value); values of a level outside its lanes are read by no
+// needed point.  Level S is stored on lanes S .. 63-S (from x = 1 and up to
+// x = nx-2 at the grid's edges) and the chunk's rows.  Intermediate levels
+// stay in the storage type's own arithmetic (FP64, FP32), so a pass is
+// bit-identical to S single steps.  No LDS and no barrier.
+constexpr int kMaxSteps2d = 8;
+
+template <int DT, int S, int WPB>
+__global__ __launch_bounds__(64 * WPB) void step2d_ymarch_s(Step2dArgs<DT> a, int nstrips, int nchunks, int ylen)
+{
+    using Tr = Traits<DT>;
+    using C = typename Tr::C;
+    static_assert(S >= 2 && S <= kMaxSteps2d, "two to eight steps per pass");
+    constexpr int TX = 64 - 2 * S;
+    const int lane = (int)(threadIdx.x & 63);
+    const int wid = (int)blockIdx.x * WPB + (int)(threadIdx.x >> 6);
+    if (wid >= nstrips * nchunks) return;         // whole waves
+    const int nx = a.nx, ny = a.ny;
+    const int strip = wid % nstrips, chunk = wid / nstrips;
+    const int ys = 1 + chunk * ylen, ye = min(ny - 1, ys + ylen);   // output rows ys .. ye-1
+    if (ys >= ye) return;                         // whole waves
+    const int xr = strip * TX;
+    const int x = xr + lane;
+    const int xc = min(x, nx - 1);
+    const bool ex0 = xr == 0, ex1 = xr + 64 >= nx;
+    const bool interior_x = x >= 1 && x <= nx - 2;
+    const bool out_lane = interior_x && (lane >= S || ex0) && (lane <= 63 - S || ex1);
+    const size_t sy = (size_t)nx;
+    auto row = [&](int y) __attribute__((always_inline)) { return (size_t)min(max(y, 0), ny - 1); };
+    auto ld = [&](int y) __attribute__((always_inline)) -> C { return Tr::load(a.T[(size_t)xc + sy * row(y)]); };
+    auto ldc = [&](int y) __attribute__((always_inline)) -> C {
+        return Tr::load(__builtin_nontemporal_load(a.Ci + (size_t)xc + sy * row(y)));
+    };
+
+    const int y0 = ys - S + 1;                    // level 1 reaches its first needed row
+    const int ylast = ye + S - 2;                 // level S reaches the chunk's last row
+    // level s-1's two rows below its newest one (lm: row - 2, lc: row - 1)
+    C lm[S], lc[S];
+    // lam*Ci at rows y, y-1, .., y-S+1 (level s uses cr[s-1]); loads in flight
+    C cr[S];
+#pragma unroll
+    for (int s = 1; s < S; ++s) lm[s] = lc[s] = C(0);
+    lm[0] = ld(y0 - 1);
+    lc[0] = ld(y0);
+    C tA = ld(y0 + 1), tB = ld(y0 + 2);           // level 0 at rows y+1 and y+2
+#pragma unroll
+    for (int j = 0; j < S; ++j) cr[j] = a.lam * ldc(y0 - j);
+    C cA = ldc(y0 + 1);                           // Ci at row y+1
+    for (int y = y0; y <= ylast; ++y) {
+        const C tC = ld(y + 3);
+        const C cB = ldc(y + 2);
+        C fresh = tA;                             // level s-1 at row y + 2 - s
+#pragma unroll
+        for (int s = 1; s <= S; ++s) {
+            const int r = y + 1 - s;
+            const C ce = lc[s - 1];
+            const C xm = lane_shift<C, false>(ce);
+            const C xp = lane_shift<C, true>(ce);
+            const C l = fd::lap2(ce, xm, xp, lm[s - 1], fresh, a.cx, a.cy);
+            const C w = fd::update(ce, a.dt, cr[s - 1], l);
+            lm[s - 1] = ce;
+            lc[s - 1] = fresh;
+            if (s < S) {
+                fresh = (r >= 1 && r <= ny - 2 && interior_x) ? w : ce;
+            } else if (r >= ys && r < ye && out_lane) {
+                __builtin_nontemporal_store(Tr::store(w, 0), a.T2 + (size_t)x + sy * (size_t)r);
+            }
+        }
+#pragma unroll
+        for (int j = S - 1; j >= 1; --j) cr[j] = cr[j - 1];
+        cr[0] = a.lam * cA;
+        cA = cB;
+        tA = tB;
+        tB = tC;
+    }
+}
+
 }  // namespace diff3d

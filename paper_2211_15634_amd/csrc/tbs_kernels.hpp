@@ -34,24 +34,6 @@ namespace diff3d {
 // 147 us at one workgroup per CU (two-step passes: 136 us); stochastic
 // rounding fits with its raw-value rings, 136 us per step (one workgroup
 // per CU: 174 us).
-// The value of the next (UP) or previous lane of the wave (DPP wave shift by
-// one lane; the end lanes read zero, unused: the region's outermost columns
-// are never updated).
-template <class T, bool UP>
-__device__ inline T lane_shift(T v)
-{
-    constexpr int ctrl = UP ? 0x130 : 0x138;     // wave_shl:1 / wave_shr:1
-    if constexpr (sizeof(T) == 8) {
-        const int2 w = __builtin_bit_cast(int2, v);
-        const int lo = __builtin_amdgcn_mov_dpp(w.x, ctrl, 0xF, 0xF, true);
-        const int hi = __builtin_amdgcn_mov_dpp(w.y, ctrl, 0xF, 0xF, true);
-        return __builtin_bit_cast(T, int2{lo, hi});
-    } else {
-        const int w = __builtin_bit_cast(int, v);
-        return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(w, ctrl, 0xF, 0xF, true));
-    }
-}
-
 template <int DT, int S, int W0, int H0, int NTH>
 constexpr int tbs_min_waves()
 {

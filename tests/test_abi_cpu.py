@@ -397,6 +397,10 @@ def test_2d_argument_validation_without_gpu():
     assert lib.diff2d_run(p, q, r, 8, 8, *sc, -1, d3.F64, None) == d3.EINVAL
     assert lib.diff2d_run(p, q, p, 8, 8, *sc, 3, d3.F64, None) == d3.EINVAL
     assert lib.diff2d_run(p, q, r, 8, 8, *sc, 0, d3.F32, None) == d3.OK
+    for n in (0, 9, -1):
+        assert lib.diff2d_stepn(p, q, r, 8, 8, *sc, n, d3.F64, None) == d3.EINVAL
+    assert lib.diff2d_stepn(p, q, r, 8, 8, *sc, 2, d3.BF16, None) == d3.EDTYPE
+    assert lib.diff2d_stepn(p, p, r, 8, 8, *sc, 2, d3.F64, None) == d3.EINVAL
 
 
 def test_apply_validation_without_gpu():

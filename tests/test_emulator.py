@@ -199,3 +199,27 @@ def test_reverse32_within_bound_and_keep_independent():
     ra, rb = oracle.reverse(*(x.astype(np.float64) for x in (T0f, Cif, gf)), *_sc(s), 15)
     assert np.max(np.abs(a1 - ra)) <= 1e-5 * np.max(np.abs(ra))
     assert np.max(np.abs(b1 - rb)) <= 1e-4 * np.max(np.abs(rb))
+
+
+def test_emulator_embeds_the_2d_step():
+    """A 2-D field as three identical z planes with rdz = 0: the emulator's
+    middle plane takes the 2-D step, equal to numpy float32 arithmetic of
+    the 2-D expression (each operation rounded once), step after step."""
+    rng = np.random.default_rng(21)
+    T0 = rng.random((17, 23)).astype(np.float32)
+    Ci = (0.5 + 0.25 * rng.random((17, 23))).astype(np.float32)
+    lam, dt, rdx, rdy = 1.0, 2.5e-4, 22.0, 16.0
+    T3 = np.repeat(T0[None], 3, axis=0)
+    C3 = np.repeat(Ci[None], 3, axis=0)
+    got = oracle.emulate_forward(T3, C3, lam, dt, rdx, rdy, 0.0, [1] * 5, oracle.ST_F32)[1]
+    f = np.float32
+    cx, cy, lamf, dtf = f(rdx * rdx), f(rdy * rdy), f(lam), f(dt)
+    T = T0.copy()
+    for _ in range(5):
+        t = T[1:-1, 1:-1]
+        d2x = (T[1:-1, 2:] - t) - (t - T[1:-1, :-2])
+        d2y = (T[2:, 1:-1] - t) - (t - T[:-2, 1:-1])
+        T2 = T.copy()
+        T2[1:-1, 1:-1] = t + dtf * ((lamf * Ci[1:-1, 1:-1]) * (d2x * cx + d2y * cy))
+        T = T2
+    assert np.array_equal(got, T)

@@ -111,3 +111,56 @@ def test_alignment_independent(lib, dtype, shape):
         return T.clone()
 
     assert torch.equal(run(0), run(1))
+
+
+def _emulate32_2d(T0, Ci, s, nt):
+    """The FP32 emulator of the oracle on the 2-D field embedded in a 3-D one:
+    three identical z planes and rdz = 0, so the z term of the 3-D step is
+    exactly zero and its middle plane takes the 2-D step."""
+    T3 = np.repeat(T0[None].astype(np.float32), 3, axis=0)
+    C3 = np.repeat(Ci[None].astype(np.float32), 3, axis=0)
+    out = oracle.emulate_forward(T3, C3, s["lam"], s["dt"], s["rdx"], s["rdy"], 0.0, [1] * nt, oracle.ST_F32)
+    return out[1]
+
+
+STEPN_SHAPES = [(3, 3), (5, 70), (67, 3), (9, 64), (40, 65), (130, 129), (70, 257), (19, 1000)]
+
+
+@pytest.mark.parametrize("shape", STEPN_SHAPES)
+@pytest.mark.parametrize("n", range(1, 9))
+def test_stepn_bitwise(lib, shape, n):
+    """n steps in one pass: FP64 equal to the oracle, FP32 equal to the FP32
+    emulator, boundary untouched; ragged grids across several 64-lane
+    regions and y-chunks."""
+    T0, Ci, s = _inputs(shape, seed=n)
+    for tdt in (torch.float64, torch.float32):
+        T = torch.from_numpy(T0).to(tdt).cuda()
+        C = torch.from_numpy(Ci).to(tdt).cuda()
+        T2 = T.clone()
+        lib.stepn2d(T2, T, C, *_sc(s), n)
+        torch.cuda.synchronize()
+        got = T2.cpu().numpy()
+        if tdt == torch.float64:
+            np.testing.assert_array_equal(got, oracle.forward2d(T0, Ci, *_sc(s), n))
+        else:
+            np.testing.assert_array_equal(got, _emulate32_2d(T0.astype(np.float32), Ci.astype(np.float32), s, n))
+
+
+@pytest.mark.parametrize("nt", [1, 7, 8, 9, 23, 41])
+def test_run_fp32_bitwise_emulator(lib, nt):
+    """The FP32 time loop (passes of up to eight steps) equal to the FP32
+    emulator bit for bit."""
+    shape = (150, 333)
+    T0, Ci, s = _inputs(shape, seed=7)
+    T = torch.from_numpy(T0).float().cuda()
+    lib.run2d(T, torch.empty_like(T), torch.from_numpy(Ci).float().cuda(), *_sc(s), nt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(T.cpu().numpy(),
+                                  _emulate32_2d(T0.astype(np.float32), Ci.astype(np.float32), s, nt))
+
+
+def test_stepn_rejects(lib):
+    T = torch.zeros((8, 8), dtype=torch.float64, device="cuda")
+    for n in (0, 9):
+        with pytest.raises(lib.Diff3dError):
+            lib.stepn2d(T.clone(), T, T.clone(), 1.0, 1e-3, 1.0, 1.0, n)
