@@ -209,7 +209,8 @@ def large_form(d3, workloads, torch, np, dev, stream, n=1024, nt=500, C=32):
     gT0 = torch.empty_like(T0)
     gCi = torch.empty_like(T0)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    for rep in range(2):   # the first repetition warms up
+    tfs, tbs = [], []
+    for rep in range(4):   # the first repetition warms up; the median of the other three
         T.copy_(T0)
         torch.cuda.synchronize()
         ev[0].record(stream)
@@ -222,8 +223,11 @@ def large_form(d3, workloads, torch, np, dev, stream, n=1024, nt=500, C=32):
         torch.cuda.synchronize()
         log("bench: large form repetition %d: forward %.3f s, reverse %.3f s" %
             (rep, ev[0].elapsed_time(ev[1]) / 1e3, ev[2].elapsed_time(ev[3]) / 1e3))
-    tf = ev[0].elapsed_time(ev[1]) / 1e3
-    tb = ev[2].elapsed_time(ev[3]) / 1e3
+        if rep:
+            tfs.append(ev[0].elapsed_time(ev[1]) / 1e3)
+            tbs.append(ev[2].elapsed_time(ev[3]) / 1e3)
+    tf = statistics.median(tfs)
+    tb = statistics.median(tbs)
     nck = (nt + C - 1) // C
     gnorm = float(d3.norm2(gT0)) ** 0.5
     finite = bool(torch.isfinite(gT0).all() and torch.isfinite(gCi).all())
