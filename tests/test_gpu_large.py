@@ -54,3 +54,70 @@ def test_grad1024_fp32_sampled(lib):
     e_gc = float(np.max(np.abs(got_gc - ref_gc)) / max(np.max(np.abs(ref_gc)), 1e-30))
     print("1024^3 FP32 vs FP64 oracle at sampled points: T %.2e gT0 %.2e gCi %.2e" % (e_T, e_g0, e_gc), flush=True)
     assert e_T <= 1e-5 and e_g0 <= 1e-5 and e_gc <= 1e-4
+
+
+def _errors(a32, b64):
+    """(max |a - b| / max |b|, max_i |a_i - b_i| / |b_i|) over the whole
+    grid, in z-slabs to bound the temporaries."""
+    num = den = rel = 0.0
+    for z in range(0, b64.shape[0], 128):
+        a = a32[z:z + 128].double()
+        b = b64[z:z + 128]
+        d = (a - b).abs()
+        num = max(num, float(d.max()))
+        den = max(den, float(b.abs().max()))
+        rel = max(rel, float((d / b.abs().clamp_min(1e-300)).max()))
+    return num / den, rel
+
+
+def test_c5_forward_whole_grid_against_fp64(lib):
+    """The large form's forward as configured (1024^3 FP32, nt = 500, a
+    checkpoint every 32 steps) on the whole grid: every checkpoint and the
+    final state against the FP64 time loop from the same FP32 initial state
+    (the FP64 loop is bit-identical to the oracle on every grid the oracle
+    can run), and the maximum principle (constant Ci: values stay within the
+    initial range, up to a few FP32 roundings).  Error bound: each step
+    rounds a handful of FP32 operations (relative 5u, u = 2^-24) and the
+    scheme does not amplify errors, so after nt steps the normwise error is
+    at most nt * 5u = 1.5e-4; the maximum relative error is reported."""
+    n, nt, C = 1024, 500, 32
+    field4, field8 = n ** 3 * 4, n ** 3 * 8
+    ws_bytes = lib.adjoint_workspace_bytes((n, n, n), nt, C, torch.float32)
+    need = ws_bytes + 3 * field4 + 3 * field8 + 2e9
+    free, total = torch.cuda.mem_get_info()
+    if free < need + 4e9:
+        pytest.skip("needs %.0f GB of free device memory" % (need / 1e9))
+    T0f = workloads.uniform(n, n, n, workloads.SEED_T0).astype(np.float32)
+    s = oracle.scalars(n, n, n, np.full((n, n, n), 0.5))
+    sc = (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+    lo, hi = float(T0f.min()), float(T0f.max())
+    T32 = torch.from_numpy(T0f).cuda()
+    T64 = T32.double()
+    del T0f
+    Ci32 = torch.full((n, n, n), 0.5, dtype=torch.float32, device="cuda")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    lib.run(T32, torch.empty_like(T32), Ci32, *sc, nt, ckpt=ws, ckpt_every=C)
+    Ci64 = torch.full((n, n, n), 0.5, dtype=torch.float64, device="cuda")
+    S64 = torch.empty_like(T64)
+    stride = (field4 + 255) // 256 * 256
+    tol = 4 * 2.0 ** -24
+    worst = (0.0, 0.0)
+    done = 0
+    for j in range(1, (nt - 1) // C + 1):
+        lib.run(T64, S64, Ci64, *sc, j * C - done)
+        done = j * C
+        slot = ws[(j - 1) * stride:(j - 1) * stride + field4].view(torch.float32).view(n, n, n)
+        e = _errors(slot, T64)
+        worst = (max(worst[0], e[0]), max(worst[1], e[1]))
+        assert float(slot.min()) >= lo - tol and float(slot.max()) <= hi + tol, j
+    lib.run(T64, S64, Ci64, *sc, nt - done)
+    e = _errors(T32, T64)
+    torch.cuda.synchronize()
+    print("1024^3 FP32 nt=500 vs the FP64 time loop, whole grid: checkpoints normwise %.2e max rel %.2e, "
+          "final normwise %.2e max rel %.2e" % (worst[0], worst[1], e[0], e[1]), flush=True)
+    bound = nt * 5 * 2.0 ** -24
+    inside = float(T32.min()) >= lo - tol and float(T32.max()) <= hi + tol
+    del T32, T64, S64, Ci32, Ci64, ws, slot
+    torch.cuda.empty_cache()
+    assert worst[0] <= bound and e[0] <= bound
+    assert inside
