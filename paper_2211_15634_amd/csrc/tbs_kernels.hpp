@@ -115,8 +115,8 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     // plane loop (combined without short-circuiting): fewer scalar
     // instructions and no SGPR spills.  Measured faster for FP32 (1.5%),
     // BF16 with stochastic rounding (10%) and BF16 with round-to-nearest at
-    // two workgroups per CU (8%); FP64 evaluates them per use (3% faster
-    // there, for no reason visible in the code).
+    // two workgroups per CU (8%).  FP64 takes the branch-free levels below
+    // and needs neither form.
     constexpr bool kMaskTable = DT == DIFF3D_F32 || DT == DIFF3D_BF16 || DT == DIFF3D_BF16_RNE;
     // x neighbours by cross-lane moves: FP64 and FP32 with W0 = 64 (1.5%
     // faster at 512^3; the BF16 kernels, at 64 VGPRs, are slower with them)

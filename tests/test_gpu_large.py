@@ -121,3 +121,74 @@ def test_c5_forward_whole_grid_against_fp64(lib):
     torch.cuda.empty_cache()
     assert worst[0] <= bound and e[0] <= bound
     assert inside
+
+
+def _normwise(a32, b64):
+    """max |a - b| / max |b| over the whole grid, in z-slabs."""
+    num = den = 0.0
+    for z in range(0, b64.shape[0], 128):
+        b = b64[z:z + 128]
+        num = max(num, float((a32[z:z + 128].double() - b).abs().max()))
+        den = max(den, float(b.abs().max()))
+    return num / max(den, 1e-300)
+
+
+def test_c5_adjoint_whole_grid_against_fp64(lib):
+    """The large form's reverse sweep as configured (1024^3 FP32, nt = 500, a
+    checkpoint every 32 steps): gT0 and gCi on the whole grid against the
+    FP64 reverse sweep of the same FP32 inputs.  The FP64 sweep is the
+    library's (bit-identical to the oracle on every grid the oracle can run),
+    taken in five parts of 100 steps to fit in memory: part p starts from
+    T_{100p} (the FP64 time loop from T0) with the multiplier the later parts
+    returned, and the Ci gradient is the sum of the parts' (this changes only
+    the FP64 summation order of gCi).  Bounds: gT0 is the transposed time
+    loop, so as for the forward at most nt * 5u = 1.5e-4 normwise (u =
+    2^-24); gCi sums nt products of such multipliers and Laplacians, gated at
+    1e-4 of its largest magnitude."""
+    n, nt, C = 1024, 500, 32
+    parts, C64 = 5, 17
+    lp = nt // parts
+    field4, field8 = n ** 3 * 4, n ** 3 * 8
+    ws32 = lib.adjoint_workspace_bytes((n, n, n), nt, C, torch.float32)
+    ws64 = lib.adjoint_workspace_bytes((n, n, n), lp, C64, torch.float64)
+    need = max(ws32 + 5 * field4, ws64 + 8 * field8 + 3 * field4) + 2e9
+    free, total = torch.cuda.mem_get_info()
+    if free < need + 4e9:
+        pytest.skip("needs %.0f GB of free device memory" % (need / 1e9))
+    s = oracle.scalars(n, n, n, np.full((n, n, n), 0.5))
+    sc = (s["lam"], s["dt"], s["rdx"], s["rdy"], s["rdz"])
+    T0 = torch.from_numpy(workloads.uniform(n, n, n, workloads.SEED_T0).astype(np.float32)).cuda()
+    gd = torch.from_numpy(workloads.direction(n, n, n).astype(np.float32)).cuda()
+    Ci = torch.full((n, n, n), 0.5, dtype=torch.float32, device="cuda")
+    gT0, gCi = torch.empty_like(T0), torch.empty_like(T0)
+    ws = torch.empty(ws32, dtype=torch.uint8, device="cuda")
+    print("1024^3 FP32 adjoint, nt=500, C=32", flush=True)
+    lib.adjoint_run(T0, Ci, gd, gT0, gCi, ws, False, *sc, nt, C)
+    torch.cuda.synchronize()
+    del ws, Ci
+    torch.cuda.empty_cache()
+    T64 = T0.double()
+    lam = gd.double()
+    del T0, gd
+    Ci64 = torch.full((n, n, n), 0.5, dtype=torch.float64, device="cuda")
+    gtot = torch.zeros_like(T64)
+    gpart, out, Ts, S = (torch.empty_like(T64) for _ in range(4))
+    ws = torch.empty(ws64, dtype=torch.uint8, device="cuda")
+    for p in reversed(range(parts)):
+        print("FP64 reference, steps %d..%d" % (p * lp, (p + 1) * lp - 1), flush=True)
+        Ts.copy_(T64)
+        if p:
+            lib.run(Ts, S, Ci64, *sc, p * lp)
+        lib.adjoint_run(Ts, Ci64, lam, out, gpart, ws, False, *sc, lp, C64)
+        gtot += gpart
+        lam, out = out, lam
+    torch.cuda.synchronize()
+    del ws, gpart, out, Ts, S, Ci64, T64
+    torch.cuda.empty_cache()
+    e_g0, e_gc = _normwise(gT0, lam), _normwise(gCi, gtot)
+    print("1024^3 FP32 nt=500 C=32 reverse vs FP64, whole grid: gT0 normwise %.2e, gCi normwise %.2e"
+          % (e_g0, e_gc), flush=True)
+    del gT0, gCi, lam, gtot
+    torch.cuda.empty_cache()
+    assert e_g0 <= nt * 5 * 2.0 ** -24
+    assert e_gc <= 1e-4
