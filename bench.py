@@ -545,8 +545,30 @@ def main():
         ts = e0.elapsed_time(e1) / 20 / 1e3 / 100
         extra["t_step_uniform64_f64_us"] = round(ts * 1e6, 2)
         extra["teff_uniform64_f64_GBps"] = round(3 * 8 * 64 ** 3 / ts / 1e9, 1)
-        del Ts, Cs, T2s
-        log("bench: 64^3 FP64 time loop %.2f us per step" % (ts * 1e6))
+        # the same call captured once into a graph and replayed: the launches
+        # of a call go to the device together
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            d3.run(Ts, T2s, Cs, *scs, 100)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            d3.run(Ts, T2s, Cs, *scs, 100)
+        for _ in range(3):
+            graph.replay()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(20):
+            graph.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tg = e0.elapsed_time(e1) / 20 / 1e3 / 100
+        extra["t_step_uniform64_f64_graph_us"] = round(tg * 1e6, 2)
+        extra["teff_uniform64_f64_graph_GBps"] = round(3 * 8 * 64 ** 3 / tg / 1e9, 1)
+        del graph, Ts, Cs, T2s
+        log("bench: 64^3 FP64 time loop %.2f us per step (%.2f replayed from a graph)" % (ts * 1e6, tg * 1e6))
 
         # ------------------------------------------------------ 2-D form, 8192^2 FP64, nt = 100
         n2 = 8192
