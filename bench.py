@@ -588,9 +588,27 @@ def main():
         ts = e0.elapsed_time(e1) / 3 / 1e3 / 100
         extra["t_step_2d_8192_f64_us"] = round(ts * 1e6, 2)
         extra["teff_2d_8192_f64_GBps"] = round(3 * 8 * n2 * n2 / ts / 1e9, 1)
+        # the same field and time loop in the other storage forms
+        for tdt, rnd, tag, esz in ((torch.float32, "sr", "f32", 4), (torch.bfloat16, "sr", "bf16_sr", 2),
+                                   (torch.bfloat16, "rne", "bf16_rne", 2)):
+            Tq = torch.from_numpy(x2).to(dev, tdt)
+            Cq = torch.full_like(Tq, 0.5)
+            Sq = torch.empty_like(Tq)
+            d3.run2d(Tq, Sq, Cq, *sc2, 10, rounding=rnd)
+            e0.record(stream)
+            for _ in range(3):
+                d3.run2d(Tq, Sq, Cq, *sc2, 100, rounding=rnd)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tq = e0.elapsed_time(e1) / 3 / 1e3 / 100
+            extra["t_step_2d_8192_%s_us" % tag] = round(tq * 1e6, 2)
+            extra["teff_2d_8192_%s_GBps" % tag] = round(3 * esz * n2 * n2 / tq / 1e9, 1)
+            del Tq, Cq, Sq
         del T2d, C2d, S2d, x2
         torch.cuda.empty_cache()
-        log("bench: 2-D 8192^2 FP64 %.1f us per step" % (ts * 1e6))
+        log("bench: 2-D 8192^2 us per step: FP64 %.1f, FP32 %.1f, BF16-SR %.1f, BF16-RNE %.1f"
+            % (ts * 1e6, extra["t_step_2d_8192_f32_us"], extra["t_step_2d_8192_bf16_sr_us"],
+               extra["t_step_2d_8192_bf16_rne_us"]))
 
         # ------------------------------------------------------ adjoint ratio
         for tdt, tag in ((torch.float64, "f64"), (torch.float32, "f32")):

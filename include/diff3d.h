@@ -279,30 +279,39 @@ int diff3d_copy(void* dst, const void* src, size_t bytes, void* stream);
  * 3-D solver): the Fig. 1 expression without the z term,
  *   T2 = T + dt*((lam*Ci)*(d2x(T)*rdx^2 + d2y(T)*rdy^2))   on interior points,
  * on an nx x ny grid, linear index x + nx*y (x fastest); T2's boundary is not
- * written.  dtype DIFF3D_F64 or DIFF3D_F32 (DIFF3D_EDTYPE otherwise); nx, ny
- * >= 3; T2 must not overlap T or Ci (EINVAL).  Device pointers, enqueued on
- * `stream`. */
+ * written.  Storage types as for the 3-D step: FP64, FP32 and both BF16
+ * forms (FP32 arithmetic; a value is rounded to BF16 only when a state is
+ * written to memory, so BF16 results depend on the pass lengths).  Under
+ * DIFF3D_BF16 the state written after global step index k (k = cfg->sr_step
+ * + the number of steps the call has taken before that step) rounds point
+ * i = x + nx*y with the random bits the 3-D step defines for index i and
+ * step k (Philox4x32-10, key cfg->sr_seed).  Only cfg's sr_seed and sr_step
+ * apply to the 2-D form (NULL: both zero).  Unknown dtype: DIFF3D_EDTYPE;
+ * nx, ny >= 3; T2 must not overlap T or Ci (EINVAL).  Device pointers,
+ * enqueued on `stream`. */
 int diff2d_step(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt,
-                double rdx, double rdy, int dtype, void* stream);
+                double rdx, double rdy, int dtype, void* stream, const diff3d_config* cfg);
 
 /* nsteps steps of the 2-D form in one pass over memory (1 <= nsteps <=
  * DIFF2D_MAX_PASS_STEPS): the interior of T2 receives the state nsteps steps
- * after T, bit-identical to nsteps single steps (intermediate states are
- * kept in the storage type's arithmetic on chip).  Precondition: T2's
+ * after T, bit-identical to nsteps single steps for FP64 and FP32
+ * (intermediate states stay in the compute type on chip; BF16 rounds once,
+ * drawing with step index cfg->sr_step + nsteps - 1).  Precondition: T2's
  * boundary equals T's.  Same argument rules as diff2d_step; nsteps out of
  * range is EINVAL. */
 #define DIFF2D_MAX_PASS_STEPS 8
 int diff2d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
-                 double rdy, int nsteps, int dtype, void* stream);
+                 double rdy, int nsteps, int dtype, void* stream, const diff3d_config* cfg);
 
 /* nt steps of the 2-D form with the buffer swap: T2 = copy(T) first, then
  * passes of several steps each (diff2d_stepn; near-equal lengths of at most
- * 7 steps for FP64 and 8 for FP32) alternating T -> T2 -> T ...; the result
- * T_nt is left in T (T2 is scratch), bit-identical to nt single steps.  Same
+ * 7 steps for FP64 and 8 for the other types: nt = 20 with at most 8 is
+ * 7, 7, 6) alternating T -> T2 -> T ...; the result T_nt is left in T (T2
+ * is scratch), bit-identical to nt single steps for FP64 and FP32.  Same
  * argument rules as diff2d_step, plus nt >= 0 and T not overlapping Ci;
  * nt = 0 leaves T unchanged. */
 int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
-               double rdy, int nt, int dtype, void* stream);
+               double rdy, int nt, int dtype, void* stream, const diff3d_config* cfg);
 
 /* The finite-difference operators of the paper's kernel notation (Fig. 1
  * composes the step of @inn, @d2_xi, @d2_yi and @d2_zi), applied to a whole

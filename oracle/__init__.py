@@ -236,13 +236,17 @@ def emulate_forward(T0, Ci, lam: float, dt: float, rdx: float, rdy: float, rdz: 
     """The time loop in FP32 arithmetic with the given storage: T0 and Ci are
     stored values (float32, or uint16 BF16 bits), ``passes`` the pass
     lengths (states inside a pass stay in FP32; the state at the end of each
-    pass is stored).  Returns the stored final state."""
+    pass is stored).  (ny, nx) arrays select the 2-D form (rdz unused).
+    Returns the stored final state."""
     dtype = np.float32 if storage == ST_F32 else np.uint16
     T0 = np.ascontiguousarray(T0, dtype=dtype)
     Ci = np.ascontiguousarray(Ci, dtype=dtype)
-    if T0.ndim != 3 or Ci.shape != T0.shape:
-        raise ValueError("fields are two (nz, ny, nx) arrays")
-    nz, ny, nx = T0.shape
+    if T0.ndim not in (2, 3) or Ci.shape != T0.shape:
+        raise ValueError("fields are two (nz, ny, nx) arrays, or two (ny, nx) arrays for the 2-D form")
+    if T0.ndim == 2:
+        (ny, nx), nz = T0.shape, 1
+    else:
+        nz, ny, nx = T0.shape
     p = np.ascontiguousarray(passes, dtype=np.int32)
     T = np.empty_like(T0)
     rc = _load().emul_forward(_vp(T), _vp(T0), _vp(Ci), nx, ny, nz, lam, dt, rdx, rdy, rdz, _vp(p), p.size,

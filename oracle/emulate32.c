@@ -36,7 +36,10 @@
  *       lambda_k = lambda_{k+1} + Lap(mu)      every point (mu = 0 outside).
  *   - the operators of the kernel notation (@inn, @d2_xi, @d2_yi, @d2_zi
  *     and the weighted Laplacian) in FP32 on widened stored values, as the
- *     FP64 oracle defines them.
+ *     FP64 oracle defines them;
+ *   - the 2-D form (a single plane, nz = 1, linear index x + nx*y): the same
+ *     step without the z term, T2 = t + dt*((lam*Ci)*(d2x*cx + d2y*cy)),
+ *     with the same passes and rounding (index i = x + nx*y).
  * Built with -ffp-contract=off; x86-64 evaluates float expressions in FP32.
  * Layout: linear index ix + nx*(iy + ny*iz), x fastest.
  */
@@ -176,6 +179,22 @@ static void step32(float* T2, const float* T, const float* Ci, int nx, int ny, i
             }
 }
 
+/* One FP32 step of the 2-D form (a single plane) on interior points. */
+static void step2d32(float* T2, const float* T, const float* Ci, int nx, int ny, float lam, float dt, float cx,
+                     float cy)
+{
+    int iy;
+#pragma omp parallel for schedule(static)
+    for (iy = 1; iy < ny - 1; ++iy)
+        for (int ix = 1; ix < nx - 1; ++ix) {
+            const size_t i = (size_t)ix + (size_t)nx * (size_t)iy;
+            float t = T[i];
+            float d2x = (T[i + 1] - t) - (t - T[i - 1]);
+            float d2y = (T[i + (size_t)nx] - t) - (t - T[i - (size_t)nx]);
+            T2[i] = t + dt * ((lam * Ci[i]) * (d2x * cx + d2y * cy));
+        }
+}
+
 /* Stored values (storage type) -> FP32. */
 static void widen_field(float* out, const void* in, size_t n, int storage)
 {
@@ -193,9 +212,11 @@ static void widen_field(float* out, const void* in, size_t n, int storage)
  * with step index k under stochastic rounding. */
 static void store_interior(void* out, const float* x, int nx, int ny, int nz, int storage, uint64_t seed, uint64_t k)
 {
+    /* a single plane (the 2-D form) is all interior along z */
+    const int z0 = nz == 1 ? 0 : 1, z1 = nz == 1 ? 1 : nz - 1;
     int iz;
 #pragma omp parallel for schedule(static)
-    for (iz = 1; iz < nz - 1; ++iz)
+    for (iz = z0; iz < z1; ++iz)
         for (int iy = 1; iy < ny - 1; ++iy) {
             /* the Philox output of the current block of 8 points, reused
              * while consecutive points stay in it */
@@ -225,12 +246,13 @@ static void store_interior(void* out, const float* x, int nx, int ny, int nz, in
 
 /* T := T0 advanced by the passes (passes[j] steps each), storage as above;
  * the j-th stored state draws with index step0 + (steps up to and
- * including that pass) - 1.  T and T0 hold nx*ny*nz stored values. */
+ * including that pass) - 1.  T and T0 hold nx*ny*nz stored values; nz = 1
+ * selects the 2-D form (rdz unused). */
 int emul_forward(void* T, const void* T0, const void* Ci, int nx, int ny, int nz, double lam, double dt, double rdx,
                  double rdy, double rdz, const int* passes, int npasses, int storage, uint64_t seed, uint64_t step0,
                  int nthreads)
 {
-    if (nx < 3 || ny < 3 || nz < 3 || npasses < 0) return -1;
+    if (nx < 3 || ny < 3 || (nz < 3 && nz != 1) || npasses < 0) return -1;
     if (storage != ST_F32 && storage != ST_BF16_SR && storage != ST_BF16_RNE) return -1;
     for (int j = 0; j < npasses; ++j)
         if (passes[j] < 1) return -1;
@@ -255,7 +277,10 @@ int emul_forward(void* T, const void* T0, const void* Ci, int nx, int ny, int nz
         float* cur = a;
         float* nxt = b;
         for (int s = 0; s < passes[j]; ++s) {
-            step32(nxt, cur, c, nx, ny, nz, lamf, dtf, cx, cy, cz);
+            if (nz == 1)
+                step2d32(nxt, cur, c, nx, ny, lamf, dtf, cx, cy);
+            else
+                step32(nxt, cur, c, nx, ny, nz, lamf, dtf, cx, cy, cz);
             float* t = cur;
             cur = nxt;
             nxt = t;

@@ -74,9 +74,9 @@ _SIGS = {
     "diff3d_norm2": ([_vp, _sz, _i, _vp, _vp], _i),
     "diff3d_copy": ([_vp, _vp, _sz, _vp], _i),
     "diff3d_philox4x32_10": ([_u32p, _u32p, _u32p], None),
-    "diff2d_step": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _vp], _i),
-    "diff2d_run": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _vp], _i),
-    "diff2d_stepn": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _vp], _i),
+    "diff2d_step": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _vp, _vp], _i),
+    "diff2d_run": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _vp, _vp], _i),
+    "diff2d_stepn": ([_vp, _vp, _vp, _i, _i, _d, _d, _d, _d, _i, _i, _vp, _vp], _i),
     "diff3d_apply": ([_i, _vp, _vp, _i, _i, _i, _d, _d, _d, _i, _vp], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -247,18 +247,20 @@ def _field2d(t: torch.Tensor, name: str, like: torch.Tensor | None = None):
 
 
 def step2d(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float,
-           rdy: float) -> None:
-    """One step of the 2-D form: interior of T2 from T and Ci, (ny, nx) fields."""
+           rdy: float, rounding: str = "sr", cfg: Config | None = None) -> None:
+    """One step of the 2-D form: interior of T2 from T and Ci, (ny, nx) fields
+    (float64, float32 or bfloat16; ``rounding`` and ``cfg`` as for step)."""
     _field2d(T, "T")
     _field2d(T2, "T2", T)
     _field2d(Ci, "Ci", T)
     ny, nx = T.shape
     with _on(T):
-        _check(_lib.diff2d_step(_p(T2), _p(T), _p(Ci), nx, ny, lam, dt, rdx, rdy, _code(T), _stream(T)), "step2d")
+        _check(_lib.diff2d_step(_p(T2), _p(T), _p(Ci), nx, ny, lam, dt, rdx, rdy, _code(T, rounding), _stream(T),
+                                _ccfg(cfg)), "step2d")
 
 
 def stepn2d(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
-            nsteps: int) -> None:
+            nsteps: int, rounding: str = "sr", cfg: Config | None = None) -> None:
     """nsteps steps of the 2-D form in one pass: interior of T2 = the state
     nsteps steps after T (T2's boundary untouched)."""
     _field2d(T, "T")
@@ -266,20 +268,20 @@ def stepn2d(T2: torch.Tensor, T: torch.Tensor, Ci: torch.Tensor, lam: float, dt:
     _field2d(Ci, "Ci", T)
     ny, nx = T.shape
     with _on(T):
-        _check(_lib.diff2d_stepn(_p(T2), _p(T), _p(Ci), nx, ny, lam, dt, rdx, rdy, int(nsteps), _code(T), _stream(T)),
-               "stepn2d")
+        _check(_lib.diff2d_stepn(_p(T2), _p(T), _p(Ci), nx, ny, lam, dt, rdx, rdy, int(nsteps), _code(T, rounding),
+                                 _stream(T), _ccfg(cfg)), "stepn2d")
 
 
 def run2d(T: torch.Tensor, T2: torch.Tensor, Ci: torch.Tensor, lam: float, dt: float, rdx: float, rdy: float,
-          nt: int) -> None:
+          nt: int, rounding: str = "sr", cfg: Config | None = None) -> None:
     """nt steps of the 2-D form with the swap; the result is left in T."""
     _field2d(T, "T")
     _field2d(T2, "T2", T)
     _field2d(Ci, "Ci", T)
     ny, nx = T.shape
     with _on(T):
-        _check(_lib.diff2d_run(_p(T), _p(T2), _p(Ci), nx, ny, lam, dt, rdx, rdy, int(nt), _code(T), _stream(T)),
-               "run2d")
+        _check(_lib.diff2d_run(_p(T), _p(T2), _p(Ci), nx, ny, lam, dt, rdx, rdy, int(nt), _code(T, rounding),
+                               _stream(T), _ccfg(cfg)), "run2d")
 
 
 # Operators of the kernel notation (diff3d_op): interior selection, second

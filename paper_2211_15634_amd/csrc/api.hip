@@ -410,7 +410,6 @@ int diff3d_adjoint_run(const void* T0, const void* Ci, const void* gTnt, void* g
 static int check2d(const void* T2, const void* T, const void* Ci, int nx, int ny, int dtype)
 {
     if (!known_dtype(dtype)) return DIFF3D_EDTYPE;
-    if (dtype != DIFF3D_F64 && dtype != DIFF3D_F32) return DIFF3D_EDTYPE;
     if (!T2 || !T || !Ci || nx < 3 || ny < 3 || (size_t)nx * (size_t)ny >= kMaxPoints) return DIFF3D_EINVAL;
     const size_t fb = (size_t)nx * ny * elem_size(dtype);
     if (overlap(T2, fb, T, fb) || overlap(T2, fb, Ci, fb)) return DIFF3D_EINVAL;
@@ -418,40 +417,47 @@ static int check2d(const void* T2, const void* T, const void* Ci, int nx, int ny
 }
 
 int diff2d_step(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
-                double rdy, int dtype, void* stream)
+                double rdy, int dtype, void* stream, const diff3d_config* cfg)
 {
     const int rc = check2d(T2, T, Ci, nx, ny, dtype);
     if (rc) return rc;
-    return step2d_dispatch(dtype, T2, T, Ci, nx, ny, lam, dt, rdx, rdy, as_stream(stream));
+    const diff3d_config c = config_of(cfg);
+    return step2dn_dispatch(dtype, 1, T2, T, Ci, nx, ny, lam, dt, rdx, rdy, c.sr_seed, c.sr_step,
+                            as_stream(stream));
 }
 
 int diff2d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
-                 double rdy, int nsteps, int dtype, void* stream)
+                 double rdy, int nsteps, int dtype, void* stream, const diff3d_config* cfg)
 {
     const int rc = check2d(T2, T, Ci, nx, ny, dtype);
     if (rc) return rc;
     if (nsteps < 1 || nsteps > kMaxSteps2d) return DIFF3D_EINVAL;
-    return step2dn_dispatch(dtype, nsteps, T2, T, Ci, nx, ny, lam, dt, rdx, rdy, as_stream(stream));
+    const diff3d_config c = config_of(cfg);
+    return step2dn_dispatch(dtype, nsteps, T2, T, Ci, nx, ny, lam, dt, rdx, rdy, c.sr_seed,
+                            c.sr_step + (uint64_t)(nsteps - 1), as_stream(stream));
 }
 
 int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, double dt, double rdx, double rdy,
-               int nt, int dtype, void* stream)
+               int nt, int dtype, void* stream, const diff3d_config* cfg)
 {
     int rc = check2d(T2, T, Ci, nx, ny, dtype);
     if (rc) return rc;
     const size_t fb = (size_t)nx * ny * elem_size(dtype);
     if (nt < 0 || overlap(T, fb, Ci, fb)) return DIFF3D_EINVAL;
     if (nt == 0) return DIFF3D_OK;
+    const diff3d_config c = config_of(cfg);
     hipStream_t st = as_stream(stream);
     rc = copy_bytes(T2, T, fb, st);               // T2 = copy(T): both buffers carry T's boundary
-    // passes of near-equal length, at most P steps each, ping-ponging
+    // passes of near-equal length, at most P steps each, ping-ponging; the
+    // state a pass stores draws with the index of its last step
     const int P = run2d_pass_steps(dtype);
     const int m = (nt + P - 1) / P;
     void* a = T;
     void* b = T2;
     for (int i = 0, done = 0; i < m && !rc; ++i) {
         const int n = (nt - done + (m - i) - 1) / (m - i);
-        rc = step2dn_dispatch(dtype, n, b, a, Ci, nx, ny, lam, dt, rdx, rdy, st);
+        rc = step2dn_dispatch(dtype, n, b, a, Ci, nx, ny, lam, dt, rdx, rdy, c.sr_seed,
+                              c.sr_step + (uint64_t)(done + n - 1), st);
         done += n;
         void* s = a;
         a = b;

@@ -17,7 +17,20 @@ struct Step2dArgs {
     const S* __restrict__ Ci;
     int nx, ny;
     C lam, dt, cx, cy;
+    SrState sr;                                   // stochastic rounding of the stored state (BF16)
 };
+
+// The 16 random bits that round point i = x + nx*y of the stored state
+// (stochastically rounded BF16 only; the same counter layout as the 3-D
+// steps, with the 2-D linear index).
+template <int DT>
+__device__ inline uint32_t rounding2d(const Step2dArgs<DT>& a, size_t i)
+{
+    if constexpr (Traits<DT>::sr)
+        return sr_word(sr_block(a.sr, i >> 3), (unsigned)(i & 7));
+    else
+        return 0u;
+}
 
 // One wave64 owns a strip of 64 consecutive x points (lane l: x = 64*strip
 // + l) and marches along y over `ylen` output rows.  Rows y-1, y, y+1 of its
@@ -72,7 +85,10 @@ __global__ __launch_bounds__(64 * WPB) void step2d_ymarch(Step2dArgs<DT> a, int 
         const C t = rc;
         const C l = fd::lap2(t, xm, xp, rm, rp, a.cx, a.cy);
         const C w = fd::update(t, a.dt, a.lam * cc, l);
-        if (interior_x) __builtin_nontemporal_store(Tr::store(w, 0), a.T2 + (size_t)x + sy * (size_t)y);
+        if (interior_x) {
+            const size_t i = (size_t)x + sy * (size_t)y;
+            __builtin_nontemporal_store(Tr::store(w, rounding2d(a, i)), a.T2 + i);
+        }
         rm = rc;
         rc = rp;
         rp = r2;
@@ -97,8 +113,9 @@ __global__ __launch_bounds__(64 * WPB) void step2d_ymarch(Step2dArgs<DT> a, int 
 // fixed boundary value); values of a level outside its lanes are read by no
 // needed point.  Level S is stored on lanes S .. 63-S (from x = 1 and up to
 // x = nx-2 at the grid's edges) and the chunk's rows.  Intermediate levels
-// stay in the storage type's own arithmetic (FP64, FP32), so a pass is
-// bit-identical to S single steps.  No LDS and no barrier.
+// stay in the compute type (FP64, or FP32 for FP32 and BF16), so a pass is
+// bit-identical to S single steps; BF16 rounds once per pass.  No LDS and
+// no barrier.
 constexpr int kMaxSteps2d = 8;
 
 template <int DT, int S, int WPB>
@@ -159,7 +176,8 @@ __global__ __launch_bounds__(64 * WPB) void step2d_ymarch_s(Step2dArgs<DT> a, in
             if (s < S) {
                 fresh = (r >= 1 && r <= ny - 2 && interior_x) ? w : ce;
             } else if (r >= ys && r < ye && out_lane) {
-                __builtin_nontemporal_store(Tr::store(w, 0), a.T2 + (size_t)x + sy * (size_t)r);
+                const size_t i = (size_t)x + sy * (size_t)r;
+                __builtin_nontemporal_store(Tr::store(w, rounding2d(a, i)), a.T2 + i);
             }
         }
 #pragma unroll

@@ -383,24 +383,27 @@ def test_fused_reverse_configurations_fit_and_defaults_are_instantiated():
 
 
 def test_2d_argument_validation_without_gpu():
-    """The 2-D entry points reject bad arguments before any launch."""
+    """The 2-D entry points reject bad arguments before any launch (every
+    storage type is accepted; only an unknown code is EDTYPE)."""
     lib = d3._lib
     p = ctypes.c_void_p(4096)
     q = ctypes.c_void_p(1 << 30)
     r = ctypes.c_void_p(1 << 31)
     sc = (1.0, 1e-5, 10.0, 10.0)
-    assert lib.diff2d_step(p, q, r, 8, 8, *sc, d3.BF16, None) == d3.EDTYPE
-    assert lib.diff2d_step(p, q, r, 8, 8, *sc, 9, None) == d3.EDTYPE
-    assert lib.diff2d_step(None, q, r, 8, 8, *sc, d3.F64, None) == d3.EINVAL
-    assert lib.diff2d_step(p, q, r, 2, 8, *sc, d3.F64, None) == d3.EINVAL
-    assert lib.diff2d_step(p, p, r, 8, 8, *sc, d3.F64, None) == d3.EINVAL
-    assert lib.diff2d_run(p, q, r, 8, 8, *sc, -1, d3.F64, None) == d3.EINVAL
-    assert lib.diff2d_run(p, q, p, 8, 8, *sc, 3, d3.F64, None) == d3.EINVAL
-    assert lib.diff2d_run(p, q, r, 8, 8, *sc, 0, d3.F32, None) == d3.OK
-    for n in (0, 9, -1):
-        assert lib.diff2d_stepn(p, q, r, 8, 8, *sc, n, d3.F64, None) == d3.EINVAL
-    assert lib.diff2d_stepn(p, q, r, 8, 8, *sc, 2, d3.BF16, None) == d3.EDTYPE
-    assert lib.diff2d_stepn(p, p, r, 8, 8, *sc, 2, d3.F64, None) == d3.EINVAL
+    cfg = d3._ccfg(d3.Config(sr_seed=3, sr_step=4))
+    assert lib.diff2d_step(p, q, r, 8, 8, *sc, 9, None, None) == d3.EDTYPE
+    assert lib.diff2d_step(p, q, r, 8, 8, *sc, -1, None, cfg) == d3.EDTYPE
+    for code in (d3.F64, d3.F32, d3.BF16, d3.BF16_RNE):
+        assert lib.diff2d_step(None, q, r, 8, 8, *sc, code, None, None) == d3.EINVAL
+        assert lib.diff2d_step(p, q, r, 2, 8, *sc, code, None, cfg) == d3.EINVAL
+        assert lib.diff2d_step(p, p, r, 8, 8, *sc, code, None, None) == d3.EINVAL
+        assert lib.diff2d_run(p, q, r, 8, 8, *sc, -1, code, None, None) == d3.EINVAL
+        assert lib.diff2d_run(p, q, p, 8, 8, *sc, 3, code, None, cfg) == d3.EINVAL
+        assert lib.diff2d_run(p, q, r, 8, 8, *sc, 0, code, None, cfg) == d3.OK
+        for n in (0, 9, -1):
+            assert lib.diff2d_stepn(p, q, r, 8, 8, *sc, n, code, None, None) == d3.EINVAL
+        assert lib.diff2d_stepn(p, p, r, 8, 8, *sc, 2, code, None, cfg) == d3.EINVAL
+    assert lib.diff2d_stepn(p, q, r, 8, 8, *sc, 2, 7, None, None) == d3.EDTYPE
 
 
 def test_apply_validation_without_gpu():

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from helpers import stored
 
 torch = pytest.importorskip("torch")
 
@@ -222,4 +223,65 @@ def test_emulator_embeds_the_2d_step():
         T2 = T.copy()
         T2[1:-1, 1:-1] = t + dtf * ((lamf * Ci[1:-1, 1:-1]) * (d2x * cx + d2y * cy))
         T = T2
+    assert np.array_equal(got, T)
+
+
+def _step2d_f32(T, Ci, lamf, dtf, cx, cy):
+    """numpy float32 arithmetic of one 2-D step (each operation rounded once)."""
+    t = T[1:-1, 1:-1]
+    d2x = (T[1:-1, 2:] - t) - (t - T[1:-1, :-2])
+    d2y = (T[2:, 1:-1] - t) - (t - T[:-2, 1:-1])
+    T2 = T.copy()
+    T2[1:-1, 1:-1] = t + dtf * ((lamf * Ci[1:-1, 1:-1]) * (d2x * cx + d2y * cy))
+    return T2
+
+
+@pytest.mark.parametrize("storage", [oracle.ST_F32, oracle.ST_BF16_RNE], ids=("f32", "bf16_rne"))
+def test_emulator_2d_equals_the_3d_embedding(storage):
+    """The 2-D form of the emulator (a (ny, nx) field) against its 3-D form
+    on the same field as three identical z planes with rdz = 0 (whose middle
+    plane takes exactly the 2-D step), over several passes: equal stored
+    bits for FP32 and round-to-nearest BF16 storage, whose rounding does not
+    depend on the point's index."""
+    rng = np.random.default_rng(22)
+    T0 = 0.25 + rng.random((19, 37))
+    Ci = 0.5 + 0.25 * rng.random((19, 37))
+    dt_ = torch.float32 if storage == oracle.ST_F32 else torch.bfloat16
+    T0s, Cis = stored(T0, dt_), stored(Ci, dt_)
+    lam, dt, rdx, rdy = 1.0, 2.5e-4, 36.0, 18.0
+    passes = [3, 1, 4, 2]
+    got = oracle.emulate_forward(T0s, Cis, lam, dt, rdx, rdy, 0.0, passes, storage)
+    T3 = np.repeat(T0s[None], 3, axis=0)
+    C3 = np.repeat(Cis[None], 3, axis=0)
+    want = oracle.emulate_forward(T3, C3, lam, dt, rdx, rdy, 0.0, passes, storage)[1]
+    assert got.dtype == want.dtype and np.array_equal(got, want)
+
+
+def test_emulator_2d_stochastic_rounding_composition():
+    """The 2-D form with stochastically rounded BF16, two passes of two
+    steps, against its parts: numpy float32 steps, the random bits of each
+    interior point's 2-D index i = x + nx*y for the step index of the pass's
+    last step (emul_sr_bits), and the stochastic rounding primitive."""
+    rng = np.random.default_rng(23)
+    ny, nx = 13, 29
+    T0 = stored(0.25 + rng.random((ny, nx)), torch.bfloat16)
+    Ci = stored(0.5 + 0.25 * rng.random((ny, nx)), torch.bfloat16)
+    lam, dt, rdx, rdy = 1.0, 4e-4, 28.0, 12.0
+    seed, step0 = 0x1234_5678_9ABC, 40
+    got = oracle.emulate_forward(T0, Ci, lam, dt, rdx, rdy, 0.0, [2, 2], oracle.ST_BF16_SR, seed=seed, step0=step0)
+    f = np.float32
+    cx, cy, lamf, dtf = f(rdx * rdx), f(rdy * rdy), f(lam), f(dt)
+    widen = lambda h: (h.astype(np.uint32) << 16).view(np.float32)
+    C = widen(Ci)
+    T = T0.copy()
+    yy, xx = np.meshgrid(np.arange(1, ny - 1), np.arange(1, nx - 1), indexing="ij")
+    idx = (xx + nx * yy).astype(np.uint64).ravel()
+    for k in (step0 + 1, step0 + 3):
+        x = widen(T)
+        for _ in range(2):
+            x = _step2d_f32(x, C, lamf, dtf, cx, cy)
+        r = oracle.sr_bits(seed, k, idx)
+        inner = oracle.bf16_stochastic(np.ascontiguousarray(x[1:-1, 1:-1]).ravel(), r)
+        T = T.copy()
+        T[1:-1, 1:-1] = inner.reshape(ny - 2, nx - 2)
     assert np.array_equal(got, T)
