@@ -303,11 +303,13 @@ int diff2d_step(void* T2, const void* T, const void* Ci, int nx, int ny, double 
 int diff2d_stepn(void* T2, const void* T, const void* Ci, int nx, int ny, double lam, double dt, double rdx,
                  double rdy, int nsteps, int dtype, void* stream, const diff3d_config* cfg);
 
-/* nt steps of the 2-D form with the buffer swap: T2 = copy(T) first, then
- * passes of several steps each (diff2d_stepn; near-equal lengths of at most
- * 7 steps for FP64 and 8 for the other types: nt = 20 with at most 8 is
- * 7, 7, 6) alternating T -> T2 -> T ...; the result T_nt is left in T (T2
- * is scratch), bit-identical to nt single steps for FP64 and FP32.  Same
+/* nt steps of the 2-D form with the buffer swap: passes of several steps
+ * each (diff2d_stepn; near-equal lengths of at most 7 steps for FP64 and 8
+ * for the other types: nt = 20 with at most 8 is 7, 7, 6) alternating
+ * between T and T2, after T's boundary is copied into T2 (and, for an odd
+ * number of passes, all of T, the first pass then reading T2, so that the
+ * last one writes T); the result T_nt is left in T (T2 is scratch),
+ * bit-identical to nt single steps for FP64 and FP32.  Same
  * argument rules as diff2d_step, plus nt >= 0 and T not overlapping Ci;
  * nt = 0 leaves T unchanged. */
 int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, double dt, double rdx,

@@ -447,13 +447,22 @@ int diff2d_run(void* T, void* T2, const void* Ci, int nx, int ny, double lam, do
     if (nt == 0) return DIFF3D_OK;
     const diff3d_config c = config_of(cfg);
     hipStream_t st = as_stream(stream);
-    rc = copy_bytes(T2, T, fb, st);               // T2 = copy(T): both buffers carry T's boundary
     // passes of near-equal length, at most P steps each, ping-ponging; the
-    // state a pass stores draws with the index of its last step
+    // state a pass stores draws with the index of its last step.  Both
+    // buffers carry T's boundary: an even number of passes starts from T
+    // (T2 needs only the boundary), an odd number from T2 = copy(T), so the
+    // last pass always writes T
     const int P = run2d_pass_steps(dtype);
     const int m = (nt + P - 1) / P;
     void* a = T;
     void* b = T2;
+    if (m % 2) {
+        rc = copy_bytes(T2, T, fb, st);
+        a = T2;
+        b = T;
+    } else {
+        rc = boundary2d_dispatch(dtype, T2, T, nx, ny, st);
+    }
     for (int i = 0, done = 0; i < m && !rc; ++i) {
         const int n = (nt - done + (m - i) - 1) / (m - i);
         rc = step2dn_dispatch(dtype, n, b, a, Ci, nx, ny, lam, dt, rdx, rdy, c.sr_seed,

@@ -36,6 +36,25 @@ __global__ __launch_bounds__(256) void boundary_copy(S* __restrict__ dst, const 
     }
 }
 
+// dst = src on the four edges of an nx*ny plane (corners written twice with
+// the same value).
+template <class S>
+__global__ __launch_bounds__(256) void boundary_copy2d(S* __restrict__ dst, const S* __restrict__ src, int nx, int ny)
+{
+    const size_t rows = 2 * (size_t)nx, total = rows + 2 * (size_t)ny;
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < total; k += (size_t)gridDim.x * 256) {
+        size_t i;
+        if (k < rows) {                        // y = 0 and y = ny-1
+            const size_t side = k / nx, x = k % nx;
+            i = x + (size_t)nx * (side ? (size_t)(ny - 1) : 0);
+        } else {                               // x = 0 and x = nx-1
+            const size_t q = k - rows, side = q / ny, y = q % ny;
+            i = (side ? (size_t)(nx - 1) : 0) + (size_t)nx * y;
+        }
+        dst[i] = src[i];
+    }
+}
+
 __global__ __launch_bounds__(256) void fill_zero(uint4* __restrict__ p, size_t n16, unsigned char* __restrict__ tail,
                                                  size_t ntail)
 {

@@ -67,6 +67,29 @@ int boundary_dispatch(int dtype, void* dst, const void* src, int nx, int ny, int
     return hip_status();
 }
 
+// dst = src on the edges of an nx*ny plane (the 2-D form's boundary).
+int boundary2d_dispatch(int dtype, void* dst, const void* src, int nx, int ny, hipStream_t st)
+{
+    const size_t total = 2 * ((size_t)nx + (size_t)ny);
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    switch (elem_size(dtype)) {
+    case 8:
+        boundary_copy2d<uint64_t><<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint64_t*>(dst),
+                                                                     static_cast<const uint64_t*>(src), nx, ny);
+        break;
+    case 4:
+        boundary_copy2d<uint32_t><<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint32_t*>(dst),
+                                                                     static_cast<const uint32_t*>(src), nx, ny);
+        break;
+    case 2:
+        boundary_copy2d<uint16_t><<<(unsigned)blocks, 256, 0, st>>>(static_cast<uint16_t*>(dst),
+                                                                     static_cast<const uint16_t*>(src), nx, ny);
+        break;
+    default: return DIFF3D_EDTYPE;
+    }
+    return hip_status();
+}
 
 // ------------------------------------------------------------------ reductions
 // partials: at least kRedParts doubles of device scratch; out: one double.
