@@ -85,12 +85,20 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
     // Loads use addresses clamped into the grid (T) or onto a point the
     // level-1 region needs (Ci), so they need no branch; values at points
     // outside the grid are never used by an interior update.
+    // FP64 (W0 = 64, every slot live): wave w holds the K consecutive region
+    // rows K*w .. K*w+K-1 (one per point slot), so a point's y neighbours
+    // inside that group come from the thread's own registers and only the
+    // group's outer two from LDS (512^3 four-step passes 3% faster).  FP32
+    // and BF16 run 1-7% slower that way (BF16 with stochastic rounding 13-18%:
+    // it spills) and keep slot k on row w + k*NTH/64.
+    constexpr bool kRowsY = DT == DIFF3D_F64 && W0 == 64 && A0 == K * NTH && K >= 2;
     int rr[K], cc[K], gx[K], gy[K];
     size_t base[K], cbase[K];
     bool live[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int idx = (int)threadIdx.x + k * NTH;
+        const int idx = kRowsY ? ((((int)threadIdx.x >> 6) * K + k) << 6) + ((int)threadIdx.x & 63)
+                               : (int)threadIdx.x + k * NTH;
         live[k] = idx < A0;
         rr[k] = live[k] ? idx / W0 : 0;
         cc[k] = live[k] ? idx % W0 : 0;
@@ -324,6 +332,10 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
         C prev[K];                          // level s-1 at plane z+1 (fresh output)
 #pragma unroll
         for (int k = 0; k < K; ++k) prev[k] = t0[2][k];
+        // level s-1 of slot j at the plane level s is computed at
+        auto centre = [&](int s, int j) __attribute__((always_inline)) -> C {
+            return s == 1 ? t0[1][j] : u[s - 2][1][j];
+        };
 #pragma unroll
         for (int s = 1; s <= S; ++s) {
             const int z = p - s + 1;
@@ -345,8 +357,8 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
                         xm = (&lds[s - 1][rbuf][rr[k] + 1][0])[cc[k] - 1];
                         xp = (&lds[s - 1][rbuf][rr[k] + 1][0])[cc[k] + 1];
                     }
-                    const C ym = lds[s - 1][rbuf][rr[k]][cc[k]];
-                    const C yp = lds[s - 1][rbuf][rr[k] + 2][cc[k]];
+                    const C ym = (kRowsY && k > 0) ? centre(s, k - 1) : lds[s - 1][rbuf][rr[k]][cc[k]];
+                    const C yp = (kRowsY && k < K - 1) ? centre(s, k + 1) : lds[s - 1][rbuf][rr[k] + 2][cc[k]];
                     const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, lamci(s, k), a);
                     if (s < S) {
                         out[k] = (zin && ixy[k]) ? w : ce;
@@ -377,8 +389,8 @@ __global__ __launch_bounds__(NTH, (tbs_min_waves<DT, S, W0, H0, NTH>())) void st
                 if (zact && (kMaskTable ? act[s][k] : in_level(k, s) && interior_xy(k))) {
                     const C xm = kLaneX ? xmd : lds[s - 1][rbuf][rr[k] + 1][cc[k] - 1];
                     const C xp = kLaneX ? xpd : lds[s - 1][rbuf][rr[k] + 1][cc[k] + 1];
-                    const C ym = lds[s - 1][rbuf][rr[k]][cc[k]];
-                    const C yp = lds[s - 1][rbuf][rr[k] + 2][cc[k]];
+                    const C ym = (kRowsY && k > 0) ? centre(s, k - 1) : lds[s - 1][rbuf][rr[k]][cc[k]];
+                    const C yp = (kRowsY && k < K - 1) ? centre(s, k + 1) : lds[s - 1][rbuf][rr[k] + 2][cc[k]];
                     const C w = stencil_point_lc<DT>(ce, xm, xp, ym, yp, zm, zp, lamci(s, k), a);
                     if (s < S) {
                         v = w;
