@@ -21,7 +21,10 @@ namespace diff3d {
 // whole region rows (coalesced).  Every thread keeps the same region points
 // at every level, so the z-history of a point (three planes per level, four
 // for the input with its prefetch) stays in that thread's registers; x and y
-// neighbours come from the level's plane staged in LDS.  Per plane iteration
+// neighbours come from the level's plane staged in LDS (with whole rows per
+// wave, x neighbours from the adjacent lanes instead, and for FP64 the y
+// neighbour inside a wave's pair of rows from the thread's other point).
+// Per plane iteration
 // p, level s is computed at plane p - s + 1 from level s-1 (its planes
 // p-s .. p-s+2), which is one LDS barrier per plane.
 // Intermediate levels stay in the compute type (FP64 or FP32) on chip; only
