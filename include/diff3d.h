@@ -60,7 +60,7 @@ typedef enum {
 typedef enum {
     DIFF3D_KERNEL_AUTO = 0,    /* the fastest validated variant: z-march single steps; in
                                   diff3d_run S-step passes (S = 4 for both BF16 forms;
-                                  FP64: S = 4, 3 on x-y planes of at most 128^2 points;
+                                  FP64: S = 4, 3 on x-y planes of at most 160^2 points;
                                   FP32: S = 4, 3 on x-y planes above 768^2 points); in
                                   diff3d_adjoint_run fused three-step reverse passes */
     DIFF3D_KERNEL_NAIVE = 1,   /* one thread per point, neighbours from cache */

@@ -361,9 +361,10 @@ int pass_dispatch(int dtype, void* T2, const void* T, const void* Ci, int nx, in
 constexpr size_t kF32FourStepMaxPlane = (size_t)768 * 768;
 // FP64 on small grids, where a launch holds few workgroups and each z-chunk
 // is short, is faster with three-step passes (us per step, S = 3 / S = 4:
-// 64^3 3.78 / 4.27, 128^3 7.68 / 8.70; 192^3 16.8 / 16.1): three steps on
-// x-y planes of at most 128^2 points.
-constexpr size_t kF64ThreeStepMaxPlane = (size_t)128 * 128;
+// 64^3 3.80 / 4.14, 96^3 5.17 / 5.34, 128^3 7.35 / 7.43, 160^3 9.68 / 10.26;
+// 192^3 15.1 / 14.4, 256^3 33.1 / 32.8): three steps on x-y planes of at
+// most 160^2 points.
+constexpr size_t kF64ThreeStepMaxPlane = (size_t)160 * 160;
 
 int tbs_default_steps(int dtype, int nx, int ny)
 {

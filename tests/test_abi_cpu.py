@@ -222,13 +222,13 @@ def test_pass_plan_rules():
             assert _plan((9, 9, 9), nt, f64, C, cfg) == expect(nt, C, S, False), (nt, C, S)
             assert sum(_plan((9, 9, 9), nt, f64, C, cfg)) == nt
         assert _plan((9, 9, 9), nt, f64, C) == expect(nt, C, 3, True), (nt, C)
-        assert _plan((9, 129, 128), nt, f64, C) == expect(nt, C, 4, True), (nt, C)
+        assert _plan((9, 161, 160), nt, f64, C) == expect(nt, C, 4, True), (nt, C)
         assert _plan((9, 9, 9), nt, f64, C, d3.Config(kernel=d3.KERNEL_ZMARCH)) == [1] * nt
         assert _plan((9, 9, 9), nt, f64, C, d3.Config(kernel=d3.KERNEL_TB2)) == expect(nt, C, 2, True)
-    # FP64 takes three-step passes on planes of at most 128^2 points, FP32
+    # FP64 takes three-step passes on planes of at most 160^2 points, FP32
     # on planes above 768^2 points
-    assert set(_plan((4, 128, 128), 12, f64)) == {3}
-    assert set(_plan((4, 129, 128), 12, f64)) == {4}
+    assert set(_plan((4, 160, 160), 12, f64)) == {3}
+    assert set(_plan((4, 161, 160), 12, f64)) == {4}
     assert set(_plan((4, 769, 768), 12, torch.float32)) == {3}
     assert set(_plan((4, 768, 768), 12, torch.float32)) == {4}
     L = d3._lib
