@@ -47,7 +47,9 @@ struct RevArgs {
 // Lap(F_{S-j}) is formed 2j-2 iterations before level j uses it and waits in
 // a register ring.  x/y neighbours of F_f and mu_j come from their planes
 // staged in double-buffered LDS in the previous iteration (one barrier per
-// plane); z neighbours from registers.  Loads are issued one or two plane
+// plane; with two points per thread on adjacent rows, the y neighbour across
+// the pair from the other point's registers); z neighbours from registers.
+// Loads are issued one or two plane
 // iterations before the one that uses them, from addresses clamped into the
 // grid (values outside the grid are never used).
 template <int DT, int S, int W0, int H0, int NTH>
