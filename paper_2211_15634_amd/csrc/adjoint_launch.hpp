@@ -147,8 +147,9 @@ constexpr int kMaxRevSteps = 3;
 
 // Measured reverse sweeps: 256^3, nt = 200, C = 14: FP64 40.3 ms with
 // two-step kernels over recomputed states, 22.1 ms with three-step passes on
-// 64 x 16 regions; FP32 21.5 ms and 13.7 ms (64 x 32 regions).  1024^3 FP32,
-// nt = 500, C = 32: 3.26 s and 1.81 s.
+// 64 x 16 regions (20.6-21.0 ms with the later kernel changes); FP32 21.5 ms
+// and 13.7 ms (64 x 32 regions; 13.4 ms with paired rows).  1024^3 FP32,
+// nt = 500, C = 32: 3.26 s and 1.81 s (1.77 s).
 template <int DT>
 struct RevDefaults;
 template <> struct RevDefaults<DIFF3D_F64> {
