@@ -11,7 +11,10 @@ driver), plus reduced-precision storage and a checkpointed adjoint.
 
 Fields are torch tensors of shape (nz, ny, nx), contiguous, on the GPU, of
 dtype float64, float32 or bfloat16 (x is the contiguous axis, as in the
-paper's column-major Julia arrays).
+paper's column-major Julia arrays); the 2-D form (step2d, stepn2d, run2d)
+takes (ny, nx) tensors of the same dtypes.  bfloat16 fields round
+stochastically (``rounding="sr"``, keyed by ``Config.sr_seed`` and
+``Config.sr_step``) or to nearest (``rounding="rne"``).
 """
 from __future__ import annotations
 
