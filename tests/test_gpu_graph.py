@@ -1,6 +1,6 @@
-"""The time loop and the reverse sweep under stream capture.
+"""The time loops (3-D and 2-D) and the reverse sweep under stream capture.
 
-diff3d_run and diff3d_adjoint_run enqueue only kernels on the caller's
+diff3d_run, diff2d_run and diff3d_adjoint_run enqueue only kernels on the caller's
 stream (fills and copies are kernels too: no memset or memcpy nodes, no host
 synchronisation, no allocation), so a caller can capture a call once into a
 graph and replay it, which removes the per-launch cost on small grids.  Every
@@ -105,3 +105,38 @@ def test_adjoint_graph_replays(lib, dtype):
     if dtype == torch.float64:
         ra, rb = oracle.reverse(T0h, Cih, g0, *sc, nt)
         assert np.array_equal(r0.cpu().numpy(), ra) and np.array_equal(rc.cpu().numpy(), rb)
+
+
+@pytest.mark.parametrize("dtype,rounding", [(torch.float64, "sr"), (torch.float32, "sr"),
+                                            (torch.bfloat16, "sr"), (torch.bfloat16, "rne")],
+                         ids=("f64", "f32", "bf16_sr", "bf16_rne"))
+@pytest.mark.parametrize("nt", [16, 23])
+def test_run2d_graph_replays(lib, dtype, rounding, nt):
+    """The 2-D time loop (an even and an odd number of passes: the loop then
+    starts from a boundary copy or from a full copy) captured and replayed."""
+    shape = (131, 517)
+    print("graph run2d", shape, nt, dtype, rounding, flush=True)
+    ny, nx = shape
+    rng = np.random.default_rng(24)
+    T0h = rng.random(shape)
+    Cih = 0.5 * (1 + 0.5 * rng.random(shape))
+    s = oracle.scalars2d(nx, ny, Cih)
+    sc = (s["lam"], s["dt"], s["rdx"], s["rdy"])
+    cfg = lib.Config(sr_seed=5, sr_step=2)
+    T0 = torch.from_numpy(T0h).to(dtype).cuda()
+    Ci = torch.from_numpy(Cih).to(dtype).cuda()
+    ref = T0.clone()
+    lib.run2d(ref, torch.empty_like(ref), Ci, *sc, nt, rounding=rounding, cfg=cfg)
+    torch.cuda.synchronize()
+    T, T2 = T0.clone(), torch.empty_like(T0)
+    g = _capture(lambda: lib.run2d(T, T2, Ci, *sc, nt, rounding=rounding, cfg=cfg))
+    for rep in range(3):
+        T.copy_(T0)
+        torch.cuda.synchronize()
+        g.replay()
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        assert _same_bits(T, ref), "replay %d differs from the eager run" % rep
+    if dtype == torch.float64:
+        assert np.array_equal(ref.cpu().numpy(), oracle.forward2d(T0h, Cih, *sc, nt))
